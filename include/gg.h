@@ -1,0 +1,232 @@
+/*
+ * gg.h -- C ABI of the MI355X (gfx950) frontier-traversal library.
+ *
+ * The library runs the frontier-driven edge traversal of "Compilation
+ * Techniques for Graph Algorithms on GPUs" (Brahmakshatriya et al., CGO 2021):
+ * edges.from(frontier).to(filter).apply(update), the operator of the paper's
+ * Algorithm Language section (BFS program figure), under the schedule
+ * choices of its Scheduling Language section (SimpleGPUSchedule and
+ * HybridGPUSchedule tables): load balancing, push/pull direction, frontier
+ * representation and creation, deduplication, delta-stepping buckets,
+ * EdgeBlocking and kernel fusion.
+ *
+ * Conventions for every entry point:
+ *   - Every call returns a gg_status; no C++ exception crosses this ABI.
+ *     On failure gg_last_error() returns a thread-local message.
+ *   - Graph arrays passed to gg_graph_create_csr are host pointers unless
+ *     GG_INPUT_DEVICE is set. The library copies them: the caller keeps
+ *     ownership of its arrays.
+ *   - Output arrays (depth, dist, label, rank, sigma, delta) are caller-owned
+ *     DEVICE memory (e.g. a torch tensor's data_ptr) of the stated length.
+ *   - Calls are stream-ordered on `stream` (0 = the null stream) and return
+ *     once the result is complete on that stream.
+ *   - A graph is immutable after creation apart from cached derived layouts;
+ *     queries on one graph may run concurrently on distinct streams (each call
+ *     takes a private workspace from the graph's mutex-protected pool).
+ *   - The library allocates device memory only for the graph copy, derived
+ *     layouts and cached workspaces; everything is released by
+ *     gg_graph_destroy.
+ */
+#ifndef GG_H
+#define GG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* hipStream_t without pulling in HIP headers */
+typedef struct ihipStream_t *gg_stream_t;
+
+typedef enum {
+    GG_OK = 0,
+    GG_ERR_INVALID_ARG = 1,
+    GG_ERR_OUT_OF_MEMORY = 2,
+    GG_ERR_DEVICE = 3,               /* a HIP call failed; message keeps hipError text */
+    GG_ERR_UNSUPPORTED_SCHEDULE = 4, /* combination the operator cannot run */
+    GG_ERR_OVERFLOW = 5,             /* result not representable (SSSP dist, BC sigma) */
+    GG_ERR_ADMISSION = 6,            /* serving: query can never fit the memory budget */
+    GG_ERR_NOT_FOUND = 7,            /* serving: unknown ticket */
+    GG_ERR_NOT_READY = 8             /* serving: result not complete yet */
+} gg_status;
+
+/* ---- algorithms ---------------------------------------------------------- */
+typedef enum { GG_ALGO_BFS = 0, GG_ALGO_SSSP = 1, GG_ALGO_CC = 2, GG_ALGO_PR = 3, GG_ALGO_BC = 4 } gg_algo;
+
+/* ---- schedule (SimpleGPUSchedule / HybridGPUSchedule tables) --------------- */
+/* configLoadBalance: work-to-thread mapping of the active edges
+   (GPU Optimization Space section, "Load Balancing"; ETWC algorithm). */
+typedef enum {
+    GG_LB_VERTEX_BASED = 0, /* one lane per active vertex */
+    GG_LB_WM = 1,           /* active vertices split evenly over wavefronts */
+    GG_LB_CM = 2,           /* active vertices split evenly over workgroups */
+    GG_LB_STRICT = 3,       /* every lane gets the same number of edges */
+    GG_LB_TWC = 4,          /* grid-wide degree binning into lane/wave/workgroup tiers */
+    GG_LB_ETWC = 5,         /* per-workgroup chunking into workgroup/wave/lane stages */
+    GG_LB_EDGE_ONLY = 6     /* edge-parallel over all edges (COO) */
+} gg_load_balance;
+
+/* configDirection */
+typedef enum { GG_PUSH = 0, GG_PULL = 1 } gg_direction;
+/* frontier representation read by PULL (configDirection's optional argument) */
+typedef enum { GG_REP_BOOLMAP = 0, GG_REP_BITMAP = 1 } gg_frontier_rep;
+/* configFrontierCreation */
+typedef enum { GG_CREATE_FUSED = 0, GG_CREATE_UNFUSED_BOOLMAP = 1, GG_CREATE_UNFUSED_BITMAP = 2 } gg_frontier_creation;
+/* configDeduplication strategy */
+typedef enum { GG_DEDUP_MONOTONIC_COUNTERS = 0, GG_DEDUP_BITMAP = 1, GG_DEDUP_BOOLMAP = 2 } gg_dedup_type;
+
+typedef struct {
+    int32_t load_balance;      /* gg_load_balance, default VERTEX_BASED */
+    int32_t edge_blocking;     /* 0/1: EdgeBlocking (all-edges operators only) */
+    int32_t blocking_size;     /* vertices per EdgeBlocking segment, default 2^20 */
+    int32_t direction;         /* gg_direction, default PUSH */
+    int32_t pull_rep;          /* gg_frontier_rep, default BOOLMAP */
+    int32_t frontier_creation; /* gg_frontier_creation, default FUSED */
+    int32_t dedup_enable;      /* 0/1, default 1 */
+    int32_t dedup_type;        /* gg_dedup_type, default MONOTONIC_COUNTERS */
+    int32_t delta;             /* configDelta: bucket width for SSSP, default 1 */
+    int32_t kernel_fusion;     /* configKernelFusion: 0/1, default 0 (see DESIGN) */
+} gg_simple_schedule;
+
+/* HybridGPUSchedule with the INPUT_VERTEXSET_SIZE criterion: an iteration
+   runs s2 when |input frontier| > threshold * n, else s1. With hybrid == 0
+   only s1 is used. Kernel fusion of the loop is taken from s1. */
+typedef struct {
+    int32_t hybrid;
+    float threshold;
+    gg_simple_schedule s1;
+    gg_simple_schedule s2;
+} gg_schedule;
+
+typedef enum {
+    GG_PRESET_DEFAULT = 0,     /* PUSH, VERTEX_BASED, FUSED, dedup monotonic */
+    GG_PRESET_BFS_HYBRID = 1,  /* the paper's direction-optimising BFS schedule */
+    GG_PRESET_ROAD_FUSED = 2,  /* PUSH, fused loop (high-diameter graphs) */
+    GG_PRESET_POWERLAW = 3     /* ETWC push / hybrid for power-law graphs */
+} gg_preset;
+
+/* ---- statistics ------------------------------------------------------------ */
+#define GG_STATS_COUNT_EDGES 1u /* request device counters of examined edges */
+typedef struct {
+    uint32_t flags;            /* in: GG_STATS_* requests */
+    int32_t iterations;        /* levels / rounds / bucket phases executed */
+    int32_t push_iterations;   /* iterations run with a PUSH schedule */
+    int32_t pull_iterations;   /* iterations run with a PULL schedule */
+    int32_t launches;          /* kernels launched by the call */
+    int32_t buckets;           /* SSSP: non-empty buckets processed */
+    int32_t fused;             /* 1 if the loop ran as one persistent launch */
+    int64_t edges_examined;    /* with GG_STATS_COUNT_EDGES */
+    int64_t vertices_processed;/* with GG_STATS_COUNT_EDGES: sum of frontier sizes */
+    double device_ms;          /* wall time of the call's device work */
+} gg_stats;
+
+/* ---- errors ------------------------------------------------------------------ */
+const char *gg_status_string(gg_status s);
+/* Thread-local message describing the last failure on this thread ("" if none). */
+const char *gg_last_error(void);
+/* Library version string. */
+const char *gg_version(void);
+
+/* ---- graph ----------------------------------------------------------------------- */
+typedef struct gg_graph gg_graph;
+
+#define GG_INPUT_DEVICE 1u /* row_ptr/col/w are device pointers */
+#define GG_VALIDATE 2u     /* O(m) check: row_ptr[0]=0, monotone, row_ptr[n]=m,
+                              0<=col<n, rows strictly ascending, no self-loops */
+#define GG_SYMMETRIC 4u    /* caller asserts (u,v) in E <=> (v,u) in E; required by
+                              PULL and by the undirected algorithms (CC, BC, PR) */
+
+/*
+ * Build a device-resident CSR graph (the `load` of the paper's BFS program).
+ * n >= 1 vertices, m directed entries (0 <= m < 2^31); row_ptr[n+1], col[m]
+ * int32; w[m] uint32 edge weights or NULL (SSSP requires weights in
+ * [1, 2^31/n]). The arrays are copied. Errors: GG_ERR_INVALID_ARG for bad
+ * sizes/pointers or a failed GG_VALIDATE check, GG_ERR_OUT_OF_MEMORY,
+ * GG_ERR_DEVICE.
+ */
+gg_status gg_graph_create_csr(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col,
+                              const uint32_t *w, uint32_t flags, gg_stream_t stream,
+                              gg_graph **out);
+/* Frees the graph, its derived layouts and cached workspaces. NULL is a no-op. */
+gg_status gg_graph_destroy(gg_graph *g);
+gg_status gg_graph_info(const gg_graph *g, int32_t *n, int64_t *m, int32_t *has_weights,
+                        int32_t *symmetric);
+
+/*
+ * EdgeBlocking preprocessing (GPU-Specific Optimizations section, Algorithm
+ * for preprocessing the input graph): the COO edge list is counted per
+ * destination segment floor(dst / seg_vertices), an exclusive prefix sum
+ * gives each segment's start, and a stable scatter writes the blocked COO.
+ * Owned by the graph, cached per seg_vertices (idempotent). prep_ms (may be
+ * NULL) receives the preprocessing time.
+ */
+gg_status gg_graph_prepare_edgeblocking(gg_graph *g, int32_t seg_vertices, gg_stream_t stream,
+                                        double *prep_ms);
+/*
+ * Copy the blocked COO built by gg_graph_prepare_edgeblocking into caller
+ * device buffers src_dev[m], dst_dev[m] and host seg_start[S+1]
+ * (S = ceil(n / seg_vertices)); segment s holds entries [seg_start[s],
+ * seg_start[s+1]). GG_ERR_INVALID_ARG if that blocking was not prepared.
+ */
+gg_status gg_graph_edgeblocking_export(const gg_graph *g, int32_t seg_vertices, int32_t *src_dev,
+                                       int32_t *dst_dev, int64_t *seg_start_host,
+                                       gg_stream_t stream);
+
+/* ---- schedules ---------------------------------------------------------------------- */
+/* Defaults of the SimpleGPUSchedule table; fusion defaults to disabled. */
+gg_status gg_schedule_default(gg_schedule *s);
+gg_status gg_schedule_preset(int32_t algo, int32_t preset, gg_schedule *s);
+/* GG_OK if `algo` can run `s` on `g`, else GG_ERR_UNSUPPORTED_SCHEDULE or
+   GG_ERR_INVALID_ARG with the reason in gg_last_error(). */
+gg_status gg_schedule_validate(const gg_graph *g, int32_t algo, const gg_schedule *s);
+
+/* ---- algorithms (Evaluation section, "Algorithms") ------------------------------------- */
+/*
+ * BFS from src: depth_dev[n] int32 receives the hop count, -1 when
+ * unreachable (the depth is the unique part of the paper's parent-array BFS).
+ */
+gg_status gg_bfs(gg_graph *g, int32_t src, const gg_schedule *s, int32_t *depth_dev,
+                 gg_stream_t stream, gg_stats *stats);
+/*
+ * Delta-stepping SSSP from src with the schedule's delta (priority-queue
+ * schedule, configDelta): dist_dev[n] int32, INT32_MAX when unreachable.
+ * Requires weights. GG_ERR_OVERFLOW when a distance would exceed INT32_MAX-1.
+ */
+gg_status gg_sssp(gg_graph *g, int32_t src, const gg_schedule *s, int32_t *dist_dev,
+                  gg_stream_t stream, gg_stats *stats);
+/* Connected components (hooking + shortcutting): label_dev[n] int32 = the
+   smallest vertex id of the component. Requires GG_SYMMETRIC. */
+gg_status gg_cc(gg_graph *g, const gg_schedule *s, int32_t *label_dev, gg_stream_t stream,
+                gg_stats *stats);
+
+#define GG_PR_NO_DANGLING 1u /* drop the mass of zero-degree vertices */
+/* PageRank, fp32: `iters` power-iteration rounds from 1/n with damping
+   `damping`; zero-degree mass spread uniformly unless GG_PR_NO_DANGLING.
+   rank_dev[n] float. Requires GG_SYMMETRIC. */
+gg_status gg_pagerank(gg_graph *g, const gg_schedule *s, float damping, int32_t iters,
+                      uint32_t flags, float *rank_dev, gg_stream_t stream, gg_stats *stats);
+/* Single-source Brandes betweenness: sigma_dev[n] uint64 shortest-path
+   counts, delta_dev[n] float dependencies (delta[src] = 0). GG_ERR_OVERFLOW
+   when a path count would exceed 2^64-1. Requires GG_SYMMETRIC. */
+gg_status gg_bc(gg_graph *g, int32_t src, const gg_schedule *s, uint64_t *sigma_dev,
+                float *delta_dev, gg_stream_t stream, gg_stats *stats);
+
+/* ---- batched multi-source --------------------------------------------------------------- */
+/* k <= 64 sources (host array) in one bit-packed traversal; depth_dev is k x n
+   row-major. Bit-identical to k gg_bfs calls. */
+gg_status gg_bfs_multi(gg_graph *g, const int32_t *srcs_host, int32_t k, const gg_schedule *s,
+                       int32_t *depth_dev, gg_stream_t stream, gg_stats *stats);
+/* k <= 64 BC sources; sigma_dev / delta_dev are k x n row-major.
+   Bit-identical to k gg_bc calls. */
+gg_status gg_bc_multi(gg_graph *g, const int32_t *srcs_host, int32_t k, const gg_schedule *s,
+                      uint64_t *sigma_dev, float *delta_dev, gg_stream_t stream, gg_stats *stats);
+
+/* Device bytes of workspace a query of `algo` with k sources needs on g. */
+gg_status gg_workspace_bytes(const gg_graph *g, int32_t algo, int32_t k, size_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GG_H */

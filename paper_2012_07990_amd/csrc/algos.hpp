@@ -1,0 +1,29 @@
+// Algorithm drivers and schedule handling (declarations).
+#pragma once
+
+#include "ops.hpp"
+
+namespace gg {
+
+gg_schedule default_schedule();
+gg_schedule preset_schedule(int algo, int preset);
+// throws Error(GG_ERR_UNSUPPORTED_SCHEDULE / GG_ERR_INVALID_ARG) with the reason
+void validate_schedule(const Graph &g, int algo, const gg_schedule &s);
+size_t workspace_bytes(const Graph &g, int algo, int k);
+
+void bfs_run(Graph &G, int32_t src, const gg_schedule &s, int32_t *depth, hipStream_t stream, gg_stats *st);
+void sssp_run(Graph &G, int32_t src, const gg_schedule &s, int32_t *dist, hipStream_t stream, gg_stats *st);
+void cc_run(Graph &G, const gg_schedule &s, int32_t *label, hipStream_t stream, gg_stats *st);
+void pr_run(Graph &G, const gg_schedule &s, float damping, int iters, uint32_t flags, float *rank,
+            hipStream_t stream, gg_stats *st);
+void bc_run(Graph &G, int32_t src, const gg_schedule &s, uint64_t *sigma, float *delta, hipStream_t stream,
+            gg_stats *st);
+void msbfs_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &s, int32_t *depth, hipStream_t stream,
+               gg_stats *st);
+void msbc_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &s, uint64_t *sigma, float *delta,
+              hipStream_t stream, gg_stats *st);
+
+// EdgeBlocking preprocessing; returns milliseconds
+double edgeblock_prepare(Ctx &c, Graph &G, int32_t seg_vertices);
+
+}  // namespace gg

@@ -1,0 +1,25 @@
+// BFS edge functors and driver entry points.
+#pragma once
+
+#include "ops.hpp"
+
+namespace gg {
+
+// PUSH update: claim an unvisited destination with a compare-and-swap of its
+// level (the atomic form of the BFS program's updateEdge under toFilter).
+struct BfsPush {
+    int32_t *depth;
+    int next;
+    __device__ __forceinline__ bool active(int) const { return true; }
+    __device__ __forceinline__ bool done(int) const { return false; }
+    __device__ __forceinline__ int edge(int, int v, int) const {
+        if (depth[v] >= 0) return -1;  // filter (a stale read only costs a failed CAS)
+        return atomic_cas_i32(&depth[v], -1, next) == -1 ? v : -1;
+    }
+};
+
+
+void bfs_fused(Ctx &c, Graph &G, Workspace &ws, int32_t src, const gg_schedule &s, int32_t *depth,
+               gg_stats *st);
+
+}  // namespace gg

@@ -1,0 +1,98 @@
+// Frontier representations and output-frontier creation.
+//
+// Representations (GPU Optimization Space section, "Active Vertexset
+// Creation"; SimpleGPUSchedule table, configDirection/configFrontierCreation):
+//   sparse queue : int32 ids[cap] + int32 count
+//   boolmap      : uint8 per vertex (no atomics needed to set)
+//   bitmap       : one bit per vertex in uint64 words (wave64 ballot writes a
+//                  whole word; scattered sets need an atomic OR)
+// Deduplication (configDeduplication; "Active Vertexset Deduplication"):
+//   monotonic counters : tag[v] raised to the iteration id by an atomic max;
+//                        the raising call enqueues, the tags are never cleared
+//   bitmap / boolmap   : test-and-set of v's bit / byte, cleared every round
+#pragma once
+
+#include "common.hpp"
+
+namespace gg {
+
+enum CreateMode : int { kCreateFused = 0, kCreateBoolmap = 1, kCreateBitmap = 2 };
+enum DedupMode : int { kDedupNone = 0, kDedupMonotonic = 1, kDedupBitmap = 2, kDedupBoolmap = 3 };
+
+struct OutFrontier {
+    int32_t *q;              // FUSED: output queue
+    int32_t *count;          // FUSED: output count (device)
+    int32_t cap;             // FUSED: queue capacity
+    int32_t *overflow;       // set to 1 when an enqueue would pass `cap`
+    uint8_t *boolmap;        // UNFUSED_BOOLMAP output
+    unsigned long long *bitmap;  // UNFUSED_BITMAP output
+    int32_t *tags;           // MONOTONIC_COUNTERS
+    int32_t iter;            // MONOTONIC_COUNTERS: id of this iteration (>= 1)
+    unsigned long long *dedup_bits;  // BITMAP dedup (cleared every round)
+    unsigned *dedup_bytes;   // BOOLMAP dedup, bytes packed 4 per word (cleared every round)
+};
+
+template <int DEDUP>
+__device__ __forceinline__ bool dedup_first(const OutFrontier &o, int v) {
+    if constexpr (DEDUP == kDedupMonotonic) {
+        return atomic_max_i32(&o.tags[v], o.iter) < o.iter;
+    } else if constexpr (DEDUP == kDedupBitmap) {
+        const unsigned long long bit = 1ull << (v & 63);
+        return (atomic_or_u64(&o.dedup_bits[v >> 6], bit) & bit) == 0;
+    } else if constexpr (DEDUP == kDedupBoolmap) {
+        const unsigned sh = (unsigned)(v & 3) * 8u;
+        return ((atomic_or_u32(&o.dedup_bytes[v >> 2], 1u << sh) >> sh) & 1u) == 0;
+    } else {
+        return true;
+    }
+}
+
+// Wave-aggregated append: one atomic per wavefront, lanes write at
+// base + (number of wanting lanes below them). Every active lane of the
+// wave must call this together.
+__device__ __forceinline__ void wave_append(int32_t *q, int32_t *count, int32_t cap, int32_t *overflow,
+                                            bool want, int v) {
+    const uint64_t mask = __ballot(want);
+    if (mask == 0) return;
+    const int leader = first_lane(mask);
+    int base = 0;
+    if (lane_id() == leader) base = atomic_add_i32(count, __popcll(mask));
+    base = wave_bcast(base, leader);
+    if (want) {
+        const int pos = base + lanes_below(mask);
+        if (pos < cap) q[pos] = v;
+        else *overflow = 1;
+    }
+}
+
+// Output-frontier sink used inside edge loops (FUSED creation calls the
+// wave-aggregated append; the unfused forms mark a dense map).
+template <int CREATE, int DEDUP>
+__device__ __forceinline__ void emit(const OutFrontier &o, bool want, int v) {
+    if constexpr (CREATE == kCreateFused) {
+        if (want) want = dedup_first<DEDUP>(o, v);
+        wave_append(o.q, o.count, o.cap, o.overflow, want, v);
+    } else if constexpr (CREATE == kCreateBoolmap) {
+        if (want) o.boolmap[v] = 1;
+    } else {
+        if (want) atomic_or_u64(&o.bitmap[v >> 6], 1ull << (v & 63));
+    }
+}
+
+// ---- dense-map membership ----------------------------------------------------------
+__device__ __forceinline__ bool bit_test(const unsigned long long *bm, int v) {
+    return (bm[v >> 6] >> (v & 63)) & 1ull;
+}
+
+// ---- sources of an edge traversal ---------------------------------------------------
+struct SrcQueue {  // explicit frontier
+    const int32_t *ids;
+    int32_t size;
+    __device__ __forceinline__ int get(int i) const { return ids[i]; }
+};
+struct SrcAll {  // every vertex (topology-driven and pull traversals)
+    int32_t size;
+    __device__ __forceinline__ int get(int i) const { return i; }
+};
+
+}  // namespace gg

@@ -1,0 +1,33 @@
+// Host helpers for persistent (fused) kernels: co-resident grid sizing,
+// cooperative launch and the grid barrier's state.
+#include "fused.hpp"
+
+namespace gg {
+
+int fused_grid(const void *kernel, int per_cu, int num_cus) {
+    int occ = 0;
+    GG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, kBlock, 0));
+    require(occ >= 1, GG_ERR_DEVICE, "fused kernel cannot be resident on a compute unit");
+    const int per = per_cu < occ ? per_cu : occ;
+    return per * num_cus;
+}
+
+void launch_cooperative(Ctx &c, const void *kernel, int blocks, void **args) {
+    GG_HIP(hipLaunchCooperativeKernel(kernel, dim3(blocks), dim3(kBlock), args, 0, c.s));
+    c.launches++;
+}
+
+GridBarrier prepare_barrier(Ctx &c, Workspace &ws) {
+    ws.barrier.ensure(4);
+    fill_i32(c, reinterpret_cast<int32_t *>(ws.barrier.p), 4, 0);
+    return GridBarrier{ws.barrier.p, ws.barrier.p + 1, ws.barrier.p + 2};
+}
+
+void check_barrier(Ctx &c, Workspace &ws) {
+    unsigned v[4];
+    GG_HIP(hipMemcpyAsync(v, ws.barrier.p, sizeof(v), hipMemcpyDeviceToHost, c.s));
+    GG_HIP(hipStreamSynchronize(c.s));
+    require(v[2] == 0, GG_ERR_DEVICE, "fused kernel aborted: a grid barrier wait exceeded its limit");
+}
+
+}  // namespace gg

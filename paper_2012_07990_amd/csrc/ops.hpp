@@ -1,0 +1,153 @@
+// Host launchers for the frontier utility kernels (conversions, compaction,
+// counting, scans, fills) and the graph/workspace objects shared by the
+// algorithm drivers.
+#pragma once
+
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "common.hpp"
+
+namespace gg {
+
+// ---- launch bookkeeping ---------------------------------------------------------
+struct Ctx {
+    hipStream_t s;
+    int launches = 0;
+    unsigned long long *edge_counter = nullptr;  // device, null unless counting
+    int num_cus = 256;
+};
+
+// ---- device buffers ------------------------------------------------------------------
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    // grow-only allocation (contents not preserved)
+    void ensure(size_t count) {
+        if (count <= n && p) return;
+        release();
+        size_t bytes = (count ? count : 1) * sizeof(T);
+        GG_HIP(hipMalloc(&p, bytes));
+        n = count;
+    }
+};
+
+template <class T>
+struct HostPinned {
+    T *p = nullptr;
+    size_t n = 0;
+    HostPinned() = default;
+    HostPinned(const HostPinned &) = delete;
+    ~HostPinned() {
+        if (p) (void)hipHostFree(p);
+    }
+    void ensure(size_t count) {
+        if (count <= n && p) return;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        GG_HIP(hipHostMalloc(&p, (count ? count : 1) * sizeof(T), hipHostMallocDefault));
+        n = count;
+    }
+};
+
+// ---- per-query workspace (frontier buffers reused across iterations and calls:
+// nothing is allocated inside a traversal loop) ----------------------------------
+struct Workspace {
+    DevBuf<int32_t> q[2];                 // sparse queues
+    DevBuf<int32_t> counters;             // small device counters
+    DevBuf<uint8_t> boolmap[2];           // dense boolmaps (n, rounded up)
+    DevBuf<unsigned long long> bitmap[2]; // dense bitmaps (ceil(n/64))
+    DevBuf<int32_t> tags;                 // monotonic dedup counters
+    DevBuf<unsigned long long> dedup_bits;
+    DevBuf<unsigned> dedup_bytes;
+    DevBuf<int32_t> bins;                 // TWC tiers (3 x cap)
+    DevBuf<long long> scan;               // STRICT degree scan (cap + 1)
+    DevBuf<long long> scan_part;          // scan partials
+    DevBuf<int32_t> aux_i32[4];           // algorithm-specific
+    DevBuf<unsigned long long> aux_u64[3];
+    DevBuf<float> aux_f32[3];
+    DevBuf<double> aux_f64[2];
+    DevBuf<uint8_t> member;               // EDGE_ONLY input-frontier membership map
+    DevBuf<unsigned> barrier;             // grid barrier state for fused kernels
+    HostPinned<int32_t> h_i32;            // pinned readback slots
+    HostPinned<long long> h_i64;
+    size_t bytes() const;
+};
+
+// ---- graph ------------------------------------------------------------------------------
+struct EdgeBlocked {
+    DevBuf<int32_t> src, dst;
+    std::vector<long long> seg_start;  // host copy, S + 1 entries
+    int32_t seg_vertices = 0;
+};
+
+struct Graph {
+    int32_t n = 0;
+    int64_t m = 0;
+    bool symmetric = false;
+    bool has_weights = false;
+    DevBuf<int32_t> row_ptr, col, coo_src;
+    DevBuf<uint32_t> w;
+    int32_t max_degree = 0;
+    std::map<int32_t, std::unique_ptr<EdgeBlocked>> eb;  // per blocking size
+    std::mutex mu;
+    std::vector<std::unique_ptr<Workspace>> pool;
+    int device = 0;
+    int num_cus = 256;
+
+    DevGraph view() const {
+        return DevGraph{n, m, row_ptr.p, col.p, has_weights ? w.p : nullptr, coo_src.p};
+    }
+    std::unique_ptr<Workspace> acquire();
+    void give_back(std::unique_ptr<Workspace> ws);
+};
+
+// RAII lease of a workspace from the graph's pool
+struct Lease {
+    Graph &g;
+    std::unique_ptr<Workspace> ws;
+    explicit Lease(Graph &gr) : g(gr), ws(gr.acquire()) {}
+    ~Lease() { g.give_back(std::move(ws)); }
+    Workspace *operator->() { return ws.get(); }
+    Workspace &operator*() { return *ws; }
+};
+
+// ---- utility launchers (kernels in frontier_ops.hip) ----------------------------------
+void fill_i32(Ctx &c, int32_t *p, long long n, int32_t v);
+void fill_u8(Ctx &c, uint8_t *p, long long n, uint8_t v);
+void fill_u64(Ctx &c, unsigned long long *p, long long n, unsigned long long v);
+void fill_f32(Ctx &c, float *p, long long n, float v);
+void fill_f64(Ctx &c, double *p, long long n, double v);
+// queue -> dense map (map must be cleared first)
+void queue_to_boolmap(Ctx &c, const int32_t *q, int count, uint8_t *map);
+void queue_to_bitmap(Ctx &c, const int32_t *q, int count, unsigned long long *map);
+// dense map -> dense map (writes every word/byte of dst)
+void boolmap_to_bitmap(Ctx &c, const uint8_t *src, int n, unsigned long long *dst);
+void bitmap_to_boolmap(Ctx &c, const unsigned long long *src, int n, uint8_t *dst);
+// dense map -> queue; count must be zeroed by the caller (device int)
+void boolmap_to_queue(Ctx &c, const uint8_t *map, int n, int32_t *q, int32_t *count);
+void bitmap_to_queue(Ctx &c, const unsigned long long *map, int n, int32_t *q, int32_t *count);
+// population counts into a device int (zeroed by the caller)
+void count_boolmap(Ctx &c, const uint8_t *map, int n, int32_t *count);
+void count_bitmap(Ctx &c, const unsigned long long *map, int n, int32_t *count);
+// exclusive scan of the degrees of q[0..count) into scan[0..count] (int64)
+void degree_scan(Ctx &c, const DevGraph &g, const int32_t *q, int count, long long *scan,
+                 long long *partials);
+size_t degree_scan_partials(int count);
+
+// device -> pinned host readback of one int, then stream sync
+int32_t read_i32(Ctx &c, const int32_t *dev, int32_t *pinned);
+
+}  // namespace gg

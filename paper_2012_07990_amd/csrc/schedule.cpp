@@ -1,0 +1,154 @@
+// Schedule defaults, presets and validation (SimpleGPUSchedule and
+// HybridGPUSchedule tables of the Scheduling Language section).
+#include <string>
+
+#include "algos.hpp"
+
+namespace gg {
+
+static gg_simple_schedule simple_default() {
+    gg_simple_schedule s{};
+    s.load_balance = GG_LB_VERTEX_BASED;
+    s.edge_blocking = 0;
+    s.blocking_size = 1 << 20;
+    s.direction = GG_PUSH;
+    s.pull_rep = GG_REP_BOOLMAP;
+    s.frontier_creation = GG_CREATE_FUSED;
+    s.dedup_enable = 1;
+    s.dedup_type = GG_DEDUP_MONOTONIC_COUNTERS;
+    s.delta = 1;
+    s.kernel_fusion = 0;
+    return s;
+}
+
+gg_schedule default_schedule() {
+    gg_schedule s{};
+    s.hybrid = 0;
+    s.threshold = 0.05f;
+    s.s1 = simple_default();
+    s.s2 = simple_default();
+    return s;
+}
+
+gg_schedule preset_schedule(int algo, int preset) {
+    gg_schedule s = default_schedule();
+    switch (preset) {
+    case GG_PRESET_DEFAULT:
+        break;
+    case GG_PRESET_BFS_HYBRID:
+        // the direction-optimising BFS schedule of the paper's GPU schedule figure
+        s.hybrid = 1;
+        s.s1.direction = GG_PUSH;
+        s.s1.load_balance = GG_LB_VERTEX_BASED;
+        s.s2 = s.s1;
+        s.s2.direction = GG_PULL;
+        s.s2.pull_rep = GG_REP_BITMAP;
+        s.s2.dedup_enable = 0;
+        s.s2.frontier_creation = GG_CREATE_UNFUSED_BITMAP;
+        break;
+    case GG_PRESET_ROAD_FUSED:
+        s.s1.kernel_fusion = 1;
+        s.s1.load_balance = GG_LB_CM;
+        if (algo == GG_ALGO_SSSP) s.s1.delta = 64;
+        break;
+    case GG_PRESET_POWERLAW:
+        s.s1.load_balance = GG_LB_ETWC;
+        if (algo == GG_ALGO_BFS || algo == GG_ALGO_BC) {
+            s.hybrid = 1;
+            s.s2 = s.s1;
+            s.s2.direction = GG_PULL;
+            s.s2.pull_rep = GG_REP_BITMAP;
+            s.s2.load_balance = GG_LB_VERTEX_BASED;
+            s.s2.frontier_creation = GG_CREATE_UNFUSED_BITMAP;
+            s.s2.dedup_enable = 0;
+        }
+        if (algo == GG_ALGO_PR) s.s1.load_balance = GG_LB_STRICT, s.s1.direction = GG_PULL;
+        break;
+    default:
+        throw Error(GG_ERR_INVALID_ARG, "unknown preset");
+    }
+    return s;
+}
+
+static void bad(const std::string &m) { throw Error(GG_ERR_UNSUPPORTED_SCHEDULE, m); }
+
+static void check_simple(const Graph &g, int algo, const gg_simple_schedule &s, bool is_s2) {
+    if (s.load_balance < 0 || s.load_balance > GG_LB_EDGE_ONLY) throw Error(GG_ERR_INVALID_ARG, "bad load_balance");
+    if (s.direction != GG_PUSH && s.direction != GG_PULL) throw Error(GG_ERR_INVALID_ARG, "bad direction");
+    if (s.pull_rep != GG_REP_BOOLMAP && s.pull_rep != GG_REP_BITMAP) throw Error(GG_ERR_INVALID_ARG, "bad pull_rep");
+    if (s.frontier_creation < 0 || s.frontier_creation > GG_CREATE_UNFUSED_BITMAP)
+        throw Error(GG_ERR_INVALID_ARG, "bad frontier_creation");
+    if (s.dedup_type < 0 || s.dedup_type > GG_DEDUP_BOOLMAP) throw Error(GG_ERR_INVALID_ARG, "bad dedup_type");
+    if (s.delta < 1) throw Error(GG_ERR_INVALID_ARG, "delta must be >= 1");
+    if (s.edge_blocking && s.blocking_size < 1) throw Error(GG_ERR_INVALID_ARG, "blocking_size must be >= 1");
+    if (s.direction == GG_PULL && !g.symmetric)
+        bad("PULL needs a symmetric graph (in-edges are read from the CSR)");
+    // EdgeBlocking applies only when every edge is processed (the edge
+    // processing algorithm's note): the topology-driven PageRank sweep.
+    if (s.edge_blocking) {
+        if (algo != GG_ALGO_PR) bad("EdgeBlocking applies only to all-edges operators (PageRank)");
+        if (s.load_balance != GG_LB_EDGE_ONLY || s.direction != GG_PUSH)
+            bad("EdgeBlocking needs EDGE_ONLY load balancing in the PUSH direction");
+    }
+    switch (algo) {
+    case GG_ALGO_BFS:
+    case GG_ALGO_BC:
+        if (s.direction == GG_PULL && s.load_balance != GG_LB_VERTEX_BASED)
+            bad("PULL traversal runs VERTEX_BASED (one lane per destination)");
+        break;
+    case GG_ALGO_SSSP:
+        if (s.direction == GG_PULL) bad("SSSP runs PUSH only");
+        break;
+    case GG_ALGO_CC:
+        if (s.direction == GG_PULL) bad("CC runs PUSH only");
+        break;
+    case GG_ALGO_PR:
+        if (s.direction == GG_PULL && s.load_balance != GG_LB_VERTEX_BASED && s.load_balance != GG_LB_WM &&
+            s.load_balance != GG_LB_STRICT && s.load_balance != GG_LB_ETWC)
+            bad("PageRank PULL supports VERTEX_BASED, WM, ETWC and STRICT");
+        if (s.direction == GG_PUSH && s.load_balance != GG_LB_EDGE_ONLY)
+            bad("PageRank PUSH runs EDGE_ONLY (every edge, every round)");
+        break;
+    default:
+        throw Error(GG_ERR_INVALID_ARG, "unknown algorithm");
+    }
+    if (s.kernel_fusion && !is_s2) {
+        if (algo != GG_ALGO_BFS && algo != GG_ALGO_SSSP && algo != GG_ALGO_CC)
+            bad("kernel fusion is available for BFS, SSSP and CC loops");
+        if (s.load_balance != GG_LB_VERTEX_BASED && s.load_balance != GG_LB_WM && s.load_balance != GG_LB_CM &&
+            s.load_balance != GG_LB_ETWC)
+            bad("kernel fusion supports VERTEX_BASED, WM, CM and ETWC (device-side load balancers)");
+        if (s.frontier_creation != GG_CREATE_FUSED) bad("kernel fusion keeps the frontier as a queue (FUSED creation)");
+        if (algo != GG_ALGO_BFS && s.direction == GG_PULL) bad("fused loops run PUSH");
+    }
+}
+
+void validate_schedule(const Graph &g, int algo, const gg_schedule &s) {
+    check_simple(g, algo, s.s1, false);
+    if (s.hybrid) {
+        if (!(s.threshold > 0.f && s.threshold <= 1.f)) throw Error(GG_ERR_INVALID_ARG, "threshold must be in (0, 1]");
+        check_simple(g, algo, s.s2, true);
+        if (algo == GG_ALGO_PR || algo == GG_ALGO_CC) bad("hybrid schedules apply to frontier-driven loops (BFS, BC, SSSP)");
+        if (s.s1.kernel_fusion && s.s2.direction == GG_PUSH && s.s2.load_balance != s.s1.load_balance)
+            bad("a fused hybrid loop pushes with s1's load balancer");
+        if (s.s1.kernel_fusion && algo != GG_ALGO_BFS) bad("fused hybrid loops are available for BFS");
+    }
+}
+
+size_t workspace_bytes(const Graph &g, int algo, int k) {
+    const size_t n = (size_t)g.n, nb = (n + 255) / 256 * 256;
+    size_t b = 2 * n * 4 + 2 * nb + 2 * nb / 8 + n * 4 + 256;  // queues, maps, tags
+    switch (algo) {
+    case GG_ALGO_SSSP: b += 2 * n * 4; break;
+    case GG_ALGO_PR: b += 3 * n * 4; break;
+    case GG_ALGO_BC: b += n * 8 + n * 8; break;
+    default: break;
+    }
+    if (k > 1) {
+        b += 3 * n * 8;  // multi-source masks
+        if (algo == GG_ALGO_BC) b += (size_t)k * n * 8 + n * 4;
+    }
+    return b;
+}
+
+}  // namespace gg
