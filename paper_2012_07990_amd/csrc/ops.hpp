@@ -80,6 +80,10 @@ struct Workspace {
     DevBuf<float> aux_f32[3];
     DevBuf<double> aux_f64[2];
     DevBuf<uint8_t> member;               // EDGE_ONLY input-frontier membership map
+    DevBuf<float> pr_contrib[2];  // PageRank
+    DevBuf<double> pr_acc, pr_head, pr_tail;
+    DevBuf<double> pr_partial, pr_dangling;
+    DevBuf<unsigned> pr_done;
     DevBuf<unsigned> barrier;             // grid barrier state for fused kernels
     HostPinned<int32_t> h_i32;            // pinned readback slots
     HostPinned<long long> h_i64;

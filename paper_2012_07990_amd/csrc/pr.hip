@@ -1,0 +1,427 @@
+// PageRank: a topology-driven loop that applies every edge every round
+// (Evaluation section, "Algorithms"). Round t computes, for every vertex v,
+//   rank'(v) = (1-d)/n + d * ( sum_{u in N(v)} rank(u)/deg(u) + D/n )
+// where D is the rank held by zero-degree vertices (spread uniformly; dropped
+// with GG_PR_NO_DANGLING). contrib(u) = rank(u)/deg(u) is produced by the
+// previous round's vertex apply, together with the next round's D.
+//
+// Edge traversal forms:
+//   PULL VERTEX_BASED  one lane per vertex, neighbours summed in CSR order
+//   PULL WM            one wavefront per vertex, lane-strided sums reduced by
+//                      a fixed butterfly
+//   PULL ETWC          the ETWC stages of a workgroup accumulate per-vertex
+//                      sums in LDS (one entry per vertex per stage, stages
+//                      separated by barriers, so the order is fixed)
+//   PULL STRICT        every workgroup takes the same number of edges; rows
+//                      that cross a chunk boundary are completed from the
+//                      chunks' head/tail partial sums in the vertex apply
+//   PUSH EDGE_ONLY     every edge adds contrib(src) to acc(dst) atomically
+//   PUSH EDGE_ONLY+EB  the same over the EdgeBlocked COO, one launch per
+//                      destination segment (the edge processing algorithm)
+// Ranks and contributions are stored in FP32; every neighbour sum is
+// accumulated in FP64 (a hub's thousands of terms would otherwise lose
+// ~1e-5 absolute). Every PULL form is deterministic; the PUSH forms use FP64
+// atomic adds, whose order varies.
+#include <algorithm>
+
+#include "algos.hpp"
+#include "lb.hpp"
+
+namespace gg {
+
+constexpr int kPrChunk = kBlock * 8;  // STRICT: edges per workgroup
+
+struct PrArgs {
+    DevGraph g;
+    const float *contrib_in;
+    float *contrib_out;
+    float *rank_out;        // written on the final round only
+    float damping;
+    const double *D_in;     // dangling mass of the input round
+    double *D_out;
+    double *partials;       // per-block dangling partial sums
+    unsigned *done;         // last-block ticket
+    int dangling;           // 0: drop the dangling mass
+    double *acc;            // STRICT / PUSH accumulators (reset after read)
+    const double *head, *tail;  // STRICT chunk partials
+};
+
+__device__ __forceinline__ double pr_base(const PrArgs &a) {
+    const double n = (double)a.g.n, d = (double)a.damping;
+    return (1.0 - d) / n + d * (a.dangling ? *a.D_in : 0.0) / n;
+}
+
+__device__ __forceinline__ void pr_apply(const PrArgs &a, int v, double base, double acc, int deg, double &dl) {
+    const float nv = (float)(base + (double)a.damping * acc);
+    if (a.rank_out) a.rank_out[v] = nv;
+    a.contrib_out[v] = deg > 0 ? nv / (float)deg : 0.f;
+    if (deg == 0) dl += (double)nv;
+}
+
+// Block sum of the dangling partials, then the last block to finish reduces
+// all block partials (fixed order) into D_out.
+__device__ void pr_finish(const PrArgs &a, double dl) {
+    __shared__ double s_w[kBlock / kWave];
+    __shared__ bool s_last;
+    dl = wave_sum(dl);
+    if (lane_id() == 0) s_w[threadIdx.x / kWave] = dl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0;
+        for (int w = 0; w < kBlock / kWave; w++) t += s_w[w];
+        a.partials[blockIdx.x] = t;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned ticket = __hip_atomic_fetch_add(a.done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = ticket == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    double t = 0;
+    for (unsigned i = threadIdx.x; i < gridDim.x; i += kBlock)
+        t += __hip_atomic_load(&a.partials[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    t = wave_sum(t);
+    __syncthreads();
+    if (lane_id() == 0) s_w[threadIdx.x / kWave] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0;
+        for (int w = 0; w < kBlock / kWave; w++) s += s_w[w];
+        *a.D_out = s;
+        *a.done = 0;
+    }
+}
+
+// round 0: rank = 1/n
+__global__ __launch_bounds__(kBlock) void k_pr_init(PrArgs a) {
+    const float r0 = (float)(1.0 / (double)a.g.n);
+    double dl = 0;
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < a.g.n; v += gridDim.x * kBlock) {
+        const int deg = a.g.row_ptr[v + 1] - a.g.row_ptr[v];
+        if (a.rank_out) a.rank_out[v] = r0;
+        a.contrib_out[v] = deg > 0 ? r0 / (float)deg : 0.f;
+        if (deg == 0) dl += (double)r0;
+        if (a.acc) a.acc[v] = 0.0;
+    }
+    pr_finish(a, dl);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pr_pull_vp(PrArgs a) {
+    const double base = pr_base(a);
+    double dl = 0;
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < a.g.n; v += gridDim.x * kBlock) {
+        const int beg = a.g.row_ptr[v], end = a.g.row_ptr[v + 1];
+        double s = 0.0;
+        for (int e = beg; e < end; e++) s += (double)a.contrib_in[a.g.col[e]];
+        pr_apply(a, v, base, s, end - beg, dl);
+    }
+    pr_finish(a, dl);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pr_pull_wm(PrArgs a) {
+    const double base = pr_base(a);
+    const int lane = lane_id(), wpb = kBlock / kWave;
+    double dl = 0;
+    for (int v = blockIdx.x * wpb + threadIdx.x / kWave; v < a.g.n; v += gridDim.x * wpb) {
+        const int beg = a.g.row_ptr[v], end = a.g.row_ptr[v + 1];
+        double s = 0.0;
+        for (int e = beg + lane; e < end; e += kWave) s += (double)a.contrib_in[a.g.col[e]];
+        s = wave_sum(s);
+        if (lane == 0) pr_apply(a, v, base, s, end - beg, dl);
+    }
+    pr_finish(a, dl);
+}
+
+__device__ __forceinline__ double block_sum_d(double x, double *s_tmp) {
+    x = wave_sum(x);
+    __syncthreads();
+    if (lane_id() == 0) s_tmp[threadIdx.x / kWave] = x;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / kWave; w++) t += s_tmp[w];
+    return t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pr_pull_etwc(PrArgs a) {
+    __shared__ int q_beg[3][kBlock], q_end[3][kBlock], q_slot[3][kBlock];
+    __shared__ int q_n[3];
+    __shared__ double s_acc[kBlock];
+    __shared__ double s_tmp[kBlock / kWave];
+    const double base = pr_base(a);
+    const int tid = threadIdx.x, lane = lane_id(), wib = tid / kWave;
+    double dl = 0;
+    for (int vb = blockIdx.x * kBlock; vb < a.g.n; vb += gridDim.x * kBlock) {
+        if (tid < 3) q_n[tid] = 0;
+        s_acc[tid] = 0.0;
+        __syncthreads();
+        const int v = vb + tid;
+        int deg = 0;
+        if (v < a.g.n) {
+            int beg = a.g.row_ptr[v];
+            const int end = a.g.row_ptr[v + 1];
+            deg = end - beg;
+            int size = deg;
+            const int s2 = (size / kBlock) * kBlock;
+            if (s2 > 0) {
+                const int k = atomicAdd(&q_n[2], 1);
+                q_beg[2][k] = beg; q_end[2][k] = beg + s2; q_slot[2][k] = tid;
+                beg += s2; size -= s2;
+            }
+            const int s1 = (size / kWave) * kWave;
+            if (s1 > 0) {
+                const int k = atomicAdd(&q_n[1], 1);
+                q_beg[1][k] = beg; q_end[1][k] = beg + s1; q_slot[1][k] = tid;
+                beg += s1; size -= s1;
+            }
+            if (size > 0) {
+                const int k = atomicAdd(&q_n[0], 1);
+                q_beg[0][k] = beg; q_end[0][k] = end; q_slot[0][k] = tid;
+            }
+        }
+        __syncthreads();
+        // stage 0: one lane per entry (sequential CSR order)
+        for (int k = tid; k < q_n[0]; k += kBlock) {
+            double s = 0.0;
+            for (int e = q_beg[0][k]; e < q_end[0][k]; e++) s += (double)a.contrib_in[a.g.col[e]];
+            s_acc[q_slot[0][k]] += s;
+        }
+        __syncthreads();
+        // stage 1: one wavefront per entry
+        for (int k = wib; k < q_n[1]; k += kBlock / kWave) {
+            double s = 0.0;
+            for (int e = q_beg[1][k] + lane; e < q_end[1][k]; e += kWave) s += (double)a.contrib_in[a.g.col[e]];
+            s = wave_sum(s);
+            if (lane == 0) s_acc[q_slot[1][k]] += s;
+        }
+        __syncthreads();
+        // stage 2: the whole workgroup per entry
+        for (int k = 0; k < q_n[2]; k++) {
+            double s = 0.0;
+            for (int e = q_beg[2][k] + tid; e < q_end[2][k]; e += kBlock) s += (double)a.contrib_in[a.g.col[e]];
+            s = block_sum_d(s, s_tmp);
+            if (tid == 0) s_acc[q_slot[2][k]] += s;
+        }
+        __syncthreads();
+        if (v < a.g.n) pr_apply(a, v, base, s_acc[tid], deg, dl);
+        __syncthreads();
+    }
+    pr_finish(a, dl);
+}
+
+// STRICT: chunk c holds edges [c*C, c*C + C). Rows entirely inside a chunk
+// get their sum written to acc; the chunk's first and last rows also leave
+// their in-chunk partial sums in head[c] / tail[c].
+__global__ __launch_bounds__(kBlock) void k_pr_strict_chunks(PrArgs a, double *acc, double *head, double *tail,
+                                                             long long nchunks) {
+    __shared__ float vals[kPrChunk];
+    __shared__ int s_r0, s_r1;
+    __shared__ int long_r[kPrChunk / 32 + 1];
+    __shared__ int n_long;
+    const int tid = threadIdx.x, lane = lane_id(), wib = tid / kWave;
+    const long long m = a.g.m;
+    for (long long c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const long long E0 = c * kPrChunk, E1 = (E0 + kPrChunk < m) ? E0 + kPrChunk : m;
+#pragma unroll
+        for (int k = 0; k < kPrChunk / kBlock; k++) {
+            const long long e = E0 + k * kBlock + tid;
+            if (e < E1) vals[e - E0] = a.contrib_in[a.g.col[e]];
+        }
+        if (tid == 0) {
+            // owners of E0 and E1-1: last row r with row_ptr[r] <= e
+            int lo = 0, hi = a.g.n;  // row_ptr[lo] <= E0 < row_ptr[hi]
+            while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (a.g.row_ptr[mid] <= E0) lo = mid; else hi = mid; }
+            s_r0 = lo;
+            lo = s_r0; hi = a.g.n;
+            while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (a.g.row_ptr[mid] <= E1 - 1) lo = mid; else hi = mid; }
+            s_r1 = lo;
+            n_long = 0;
+        }
+        __syncthreads();
+        const int r0 = s_r0, r1 = s_r1;
+        // short rows (< 32 in-chunk edges): one lane each; long rows queued
+        for (int r = r0 + tid; r <= r1; r += kBlock) {
+            const long long rb = a.g.row_ptr[r], re = a.g.row_ptr[r + 1];
+            const int lo = (int)((rb > E0 ? rb : E0) - E0), hi = (int)((re < E1 ? re : E1) - E0);
+            if (hi - lo >= 32) {
+                const int k = atomicAdd(&n_long, 1);
+                long_r[k] = r;
+                continue;
+            }
+            double s = 0.0;
+            for (int i = lo; i < hi; i++) s += (double)vals[i];
+            if (rb >= E0 && re <= E1) acc[r] = s;
+            if (r == r0) head[c] = s;
+            if (r == r1) tail[c] = s;
+        }
+        __syncthreads();
+        for (int k = wib; k < n_long; k += kBlock / kWave) {
+            const int r = long_r[k];
+            const long long rb = a.g.row_ptr[r], re = a.g.row_ptr[r + 1];
+            const int lo = (int)((rb > E0 ? rb : E0) - E0), hi = (int)((re < E1 ? re : E1) - E0);
+            double s = 0.0;
+            for (int i = lo + lane; i < hi; i += kWave) s += (double)vals[i];
+            s = wave_sum(s);
+            if (lane == 0) {
+                if (rb >= E0 && re <= E1) acc[r] = s;
+                if (r == r0) head[c] = s;
+                if (r == r1) tail[c] = s;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Vertex apply after STRICT chunks (mode 0) or PUSH accumulation (mode 1).
+__global__ __launch_bounds__(kBlock) void k_pr_apply(PrArgs a, int mode) {
+    const double base = pr_base(a);
+    double dl = 0;
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < a.g.n; v += gridDim.x * kBlock) {
+        const int beg = a.g.row_ptr[v], end = a.g.row_ptr[v + 1];
+        double s = 0.0;
+        if (mode == 1) {
+            s = a.acc[v];
+            a.acc[v] = 0.0;
+        } else if (end > beg) {
+            const long long c0 = beg / kPrChunk, c1 = (end - 1) / kPrChunk;
+            if (c0 == c1) {
+                s = a.acc[v];
+            } else {
+                s = a.tail[c0];
+                for (long long c = c0 + 1; c < c1; c++) s += a.head[c];
+                s += a.head[c1];
+            }
+        }
+        pr_apply(a, v, base, s, end - beg, dl);
+    }
+    pr_finish(a, dl);
+}
+
+// PUSH EDGE_ONLY: acc[dst] += contrib[src] for every CSR entry
+__global__ __launch_bounds__(kBlock) void k_pr_push_edges(const int32_t *src, const int32_t *dst, long long lo,
+                                                          long long hi, const float *contrib, double *acc) {
+    const long long stride = (long long)gridDim.x * kBlock;
+    for (long long e = lo + (long long)blockIdx.x * kBlock + threadIdx.x; e < hi; e += stride)
+        atomic_add_f64(&acc[dst[e]], (double)contrib[src[e]]);
+}
+
+void ensure_coo(Ctx &c, Graph &G);
+
+void pr_run(Graph &G, const gg_schedule &sch, float damping, int iters, uint32_t flags, float *rank,
+            hipStream_t stream, gg_stats *st) {
+    Ctx c;
+    c.s = stream;
+    c.num_cus = G.num_cus;
+    const gg_simple_schedule &s = sch.s1;
+    const bool push = s.direction == GG_PUSH;
+    if (push) ensure_coo(c, G);
+    EdgeBlocked *eb = nullptr;
+    if (push && s.edge_blocking) {
+        edgeblock_prepare(c, G, s.blocking_size);
+        std::lock_guard<std::mutex> lk(G.mu);
+        eb = G.eb.at(s.blocking_size).get();
+    }
+    hipEvent_t e0, e1;
+    GG_HIP(hipEventCreate(&e0));
+    GG_HIP(hipEventCreate(&e1));
+    Lease ws(G);
+    const DevGraph g = G.view();
+    const int n = g.n;
+    const int lb = s.load_balance;
+    const unsigned nblk = blocks_for(n, kBlock, (unsigned)G.num_cus * 8);
+    const unsigned nblk_wm = blocks_for(n, kBlock / kWave, (unsigned)G.num_cus * 16);
+    const unsigned apply_blocks = std::max(nblk, nblk_wm);
+    ws->pr_contrib[0].ensure(n);
+    ws->pr_contrib[1].ensure(n);
+    ws->pr_partial.ensure(apply_blocks + 1);
+    ws->pr_dangling.ensure(2);
+    ws->pr_done.ensure(1);
+    const long long nchunks = (g.m + kPrChunk - 1) / kPrChunk;
+    const bool strict = !push && lb == GG_LB_STRICT;
+    if (strict || push) ws->pr_acc.ensure(n);
+    if (strict) {
+        ws->pr_head.ensure((size_t)std::max(nchunks, 1ll));
+        ws->pr_tail.ensure((size_t)std::max(nchunks, 1ll));
+    }
+    fill_i32(c, reinterpret_cast<int32_t *>(ws->pr_done.p), 1, 0);
+    GG_HIP(hipEventRecord(e0, c.s));
+
+    PrArgs a{};
+    a.g = g;
+    a.damping = damping;
+    a.dangling = (flags & GG_PR_NO_DANGLING) ? 0 : 1;
+    a.partials = ws->pr_partial.p;
+    a.done = ws->pr_done.p;
+    a.acc = (strict || push) ? ws->pr_acc.p : nullptr;
+    a.head = ws->pr_head.p;
+    a.tail = ws->pr_tail.p;
+    // round 0
+    a.contrib_out = ws->pr_contrib[0].p;
+    a.rank_out = iters == 0 ? rank : nullptr;
+    a.D_out = ws->pr_dangling.p + 0;
+    hipLaunchKernelGGL(k_pr_init, dim3(nblk), dim3(kBlock), 0, c.s, a);
+    GG_CHECK_LAUNCH();
+    c.launches++;
+    for (int t = 0; t < iters; t++) {
+        a.contrib_in = ws->pr_contrib[t & 1].p;
+        a.contrib_out = ws->pr_contrib[(t + 1) & 1].p;
+        a.D_in = ws->pr_dangling.p + (t & 1);
+        a.D_out = ws->pr_dangling.p + ((t + 1) & 1);
+        a.rank_out = t == iters - 1 ? rank : nullptr;
+        if (push) {
+            if (eb) {
+                for (size_t sg = 0; sg + 1 < eb->seg_start.size(); sg++) {
+                    const long long lo = eb->seg_start[sg], hi = eb->seg_start[sg + 1];
+                    if (hi <= lo) continue;
+                    hipLaunchKernelGGL(k_pr_push_edges, dim3(blocks_for(hi - lo, kBlock, 16384)), dim3(kBlock), 0,
+                                       c.s, eb->src.p, eb->dst.p, lo, hi, a.contrib_in, a.acc);
+                    GG_CHECK_LAUNCH();
+                    c.launches++;
+                }
+            } else if (g.m > 0) {
+                hipLaunchKernelGGL(k_pr_push_edges, dim3(blocks_for(g.m, kBlock, 16384)), dim3(kBlock), 0, c.s,
+                                   g.coo_src, g.col, 0ll, (long long)g.m, a.contrib_in, a.acc);
+                GG_CHECK_LAUNCH();
+                c.launches++;
+            }
+            hipLaunchKernelGGL(k_pr_apply, dim3(nblk), dim3(kBlock), 0, c.s, a, 1);
+        } else if (strict) {
+            if (nchunks > 0) {
+                hipLaunchKernelGGL(k_pr_strict_chunks, dim3((unsigned)std::min<long long>(nchunks, 65535)),
+                                   dim3(kBlock), 0, c.s, a, ws->pr_acc.p, ws->pr_head.p, ws->pr_tail.p, nchunks);
+                GG_CHECK_LAUNCH();
+                c.launches++;
+            }
+            hipLaunchKernelGGL(k_pr_apply, dim3(nblk), dim3(kBlock), 0, c.s, a, 0);
+        } else if (lb == GG_LB_WM) {
+            hipLaunchKernelGGL(k_pr_pull_wm, dim3(nblk_wm), dim3(kBlock), 0, c.s, a);
+        } else if (lb == GG_LB_ETWC) {
+            hipLaunchKernelGGL(k_pr_pull_etwc, dim3(nblk), dim3(kBlock), 0, c.s, a);
+        } else {
+            hipLaunchKernelGGL(k_pr_pull_vp, dim3(nblk), dim3(kBlock), 0, c.s, a);
+        }
+        GG_CHECK_LAUNCH();
+        c.launches++;
+    }
+    GG_HIP(hipEventRecord(e1, c.s));
+    GG_HIP(hipEventSynchronize(e1));
+    if (st) {
+        const uint32_t fl = st->flags;
+        *st = gg_stats{};
+        st->flags = fl;
+        float ms = 0;
+        GG_HIP(hipEventElapsedTime(&ms, e0, e1));
+        st->device_ms = ms;
+        st->iterations = iters;
+        st->launches = c.launches;
+        if (fl & GG_STATS_COUNT_EDGES) {
+            st->edges_examined = (int64_t)g.m * iters;
+            st->vertices_processed = (int64_t)n * iters;
+        }
+        if (push) st->push_iterations = iters; else st->pull_iterations = iters;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+}
+
+}  // namespace gg

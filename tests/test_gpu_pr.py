@@ -1,0 +1,89 @@
+"""GPU parity: PageRank (FP32) against the fp64 oracle for every traversal
+form, and the EdgeBlocked COO against the oracle's preprocessing (bit-exact)."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+import paper_2012_07990_amd as gg
+from gpu_util import dev_graph, host_graph, oracle_pr
+
+pytestmark = pytest.mark.gpu
+
+FORMS = {
+    "pull_vp": dict(lb="vp", direction=gg.PULL),
+    "pull_wm": dict(lb="wm", direction=gg.PULL),
+    "pull_etwc": dict(lb="etwc", direction=gg.PULL),
+    "pull_strict": dict(lb="strict", direction=gg.PULL),
+    "push_edge": dict(lb="edge_only", direction=gg.PUSH),
+    "push_eb_1k": dict(lb="edge_only", direction=gg.PUSH, edge_blocking=True, blocking_size=1000),
+    "push_eb_64": dict(lb="edge_only", direction=gg.PUSH, edge_blocking=True, blocking_size=64),
+}
+GRAPHS = ["rmat12", "rmat14", "grid64", "star5000", "cliques", "isolated7", "single", "path100k"]
+
+
+def check_pr(got, exp, dangling=True):
+    got = np.asarray(got, dtype=np.float64)
+    err = np.abs(got - exp)
+    assert err.max() <= 1e-6, "max-abs %g" % err.max()
+    assert err.sum() <= 1e-4, "sum-abs %g" % err.sum()
+    assert (err / exp).max() <= 1e-3, "max-rel %g" % (err / exp).max()
+    if dangling:
+        assert abs(got.sum() - 1.0) <= 1e-4
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+@pytest.mark.parametrize("name", GRAPHS)
+def test_pr_forms(form, name):
+    G = dev_graph(name)
+    r = G.pagerank(gg.make_schedule(**FORMS[form])).cpu().numpy()
+    check_pr(r, oracle_pr(name))
+
+
+@pytest.mark.parametrize("form", ["pull_vp", "pull_strict", "push_edge"])
+def test_pr_no_dangling(form):
+    G = dev_graph("rmat12")
+    r = G.pagerank(gg.make_schedule(**FORMS[form]), dangling=False).cpu().numpy()
+    check_pr(r, oracle_pr("rmat12", False), dangling=False)
+
+
+@pytest.mark.parametrize("iters", [0, 1, 3])
+def test_pr_iteration_counts(iters):
+    g = host_graph("rmat12")
+    G = dev_graph("rmat12")
+    exp = oracle.pagerank(g.n, g.row_ptr, g.col, 0.85, iters)
+    for form in ("pull_vp", "pull_strict", "push_edge"):
+        r = G.pagerank(gg.make_schedule(**FORMS[form]), iters=iters).cpu().numpy()
+        check_pr(r, exp)
+
+
+@pytest.mark.parametrize("form", ["pull_vp", "pull_wm", "pull_etwc", "pull_strict"])
+def test_pr_pull_deterministic(form):
+    G = dev_graph("rmat14")
+    a = G.pagerank(gg.make_schedule(**FORMS[form])).cpu().numpy()
+    b = G.pagerank(gg.make_schedule(**FORMS[form])).cpu().numpy()
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+@pytest.mark.parametrize("N", [1, 3, 64, 1000, 1 << 20])
+@pytest.mark.parametrize("name", ["rmat12", "grid64", "isolated7"])
+def test_edgeblock_layout_matches_oracle(N, name):
+    g = host_graph(name)
+    G = dev_graph(name)
+    G.prepare_edgeblocking(N)
+    assert G.prepare_edgeblocking(N) == 0.0  # cached: idempotent
+    src, dst, seg = G.edgeblocking_export(N)
+    coo_src = np.repeat(np.arange(g.n, dtype=np.int32), g.degrees())
+    es, ed, eseg = oracle.edgeblock(g.n, coo_src, g.col, N)
+    assert np.array_equal(src.cpu().numpy(), es)
+    assert np.array_equal(dst.cpu().numpy(), ed)
+    assert np.array_equal(seg, eseg)
+
+
+def test_pr_schedule_errors():
+    G = dev_graph("rmat12")
+    for kw in [dict(lb="cm", direction=gg.PULL), dict(lb="vp", direction=gg.PUSH),
+               dict(lb="vp", direction=gg.PULL, edge_blocking=True)]:
+        with pytest.raises(gg.GGError) as e:
+            G.pagerank(gg.make_schedule(**kw))
+        assert e.value.status == gg.ERR_UNSUPPORTED_SCHEDULE
