@@ -87,7 +87,8 @@ typedef struct {
     int32_t dedup_enable;      /* 0/1, default 1 */
     int32_t dedup_type;        /* gg_dedup_type, default MONOTONIC_COUNTERS */
     int32_t delta;             /* configDelta: bucket width for SSSP, default 1 */
-    int32_t kernel_fusion;     /* configKernelFusion: 0/1, default 0 (see DESIGN) */
+    int32_t kernel_fusion;     /* configKernelFusion: 0/1, default 0 (unfused, as the
+                                  paper's default PUSH schedule and fusion baseline) */
 } gg_simple_schedule;
 
 /* HybridGPUSchedule with the INPUT_VERTEXSET_SIZE criterion: an iteration
@@ -108,7 +109,8 @@ typedef enum {
 } gg_preset;
 
 /* ---- statistics ------------------------------------------------------------ */
-#define GG_STATS_COUNT_EDGES 1u /* request device counters of examined edges */
+#define GG_STATS_COUNT_EDGES 1u  /* request device counters of examined edges */
+#define GG_STATS_TIME_KERNELS 2u /* time the main edge-traversal kernel with HIP events */
 typedef struct {
     uint32_t flags;            /* in: GG_STATS_* requests */
     int32_t iterations;        /* levels / rounds / bucket phases executed */
@@ -120,6 +122,10 @@ typedef struct {
     int64_t edges_examined;    /* with GG_STATS_COUNT_EDGES */
     int64_t vertices_processed;/* with GG_STATS_COUNT_EDGES: sum of frontier sizes */
     double device_ms;          /* wall time of the call's device work */
+    double kernel_ms;          /* with GG_STATS_TIME_KERNELS: summed event time of the
+                                  main edge-traversal kernel's launches */
+    int32_t kernel_launches;   /* with GG_STATS_TIME_KERNELS: launches of that kernel */
+    char kernel_name[44];      /* with GG_STATS_TIME_KERNELS: that kernel's name */
 } gg_stats;
 
 /* ---- errors ------------------------------------------------------------------ */

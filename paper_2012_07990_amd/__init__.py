@@ -48,6 +48,7 @@ PRESET_DEFAULT, PRESET_BFS_HYBRID, PRESET_ROAD_FUSED, PRESET_POWERLAW = 0, 1, 2,
 INPUT_DEVICE, VALIDATE, SYMMETRIC = 1, 2, 4
 PR_NO_DANGLING = 1
 STATS_COUNT_EDGES = 1
+STATS_TIME_KERNELS = 2
 INT32_MAX = 2**31 - 1
 
 
@@ -80,10 +81,13 @@ class Stats(ctypes.Structure):
                 ("push_iterations", ctypes.c_int32), ("pull_iterations", ctypes.c_int32),
                 ("launches", ctypes.c_int32), ("buckets", ctypes.c_int32), ("fused", ctypes.c_int32),
                 ("edges_examined", ctypes.c_int64), ("vertices_processed", ctypes.c_int64),
-                ("device_ms", ctypes.c_double)]
+                ("device_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
+                ("kernel_launches", ctypes.c_int32), ("kernel_name", ctypes.c_char * 44)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["kernel_name"] = self.kernel_name.decode()
+        return d
 
 
 _P = ctypes.c_void_p

@@ -82,6 +82,7 @@ __global__ __launch_bounds__(kBlock) void k_bfs_fused(FusedBfsArgs a) {
     const Tid t = Tid::here();
     const int n = a.g.n;
     long long ne = 0;
+    GridBarrier bar = a.bar;
     int32_t *qin = a.q0, *qout = a.q1;
     int it = 0, pulls = 0;
     for (;;) {
@@ -112,19 +113,19 @@ __global__ __launch_bounds__(kBlock) void k_bfs_fused(FusedBfsArgs a) {
             } else {
                 for (long long i = gid; i < (n + 63) / 64; i += stride) a.map_bits[i] = 0ull;
             }
-            if (!grid_sync(a.bar)) break;
+            if (!grid_sync(bar)) break;
             for (long long i = gid; i < cnt; i += stride) {
                 const int v = qin[i];
                 if constexpr (S2 == 1) a.map_bool[v] = 1;
                 else atomic_or_u64(&a.map_bits[v >> 6], 1ull << (v & 63));
             }
-            if (!grid_sync(a.bar)) break;
+            if (!grid_sync(bar)) break;
             if constexpr (S2 == 1)
                 bfs_pull_dev<kRepBoolmap, kCreateFused>(a.g, a.depth, it + 1, a.map_bool, nullptr, o, t, ne);
             else
                 bfs_pull_dev<kRepBitmap, kCreateFused>(a.g, a.depth, it + 1, nullptr, a.map_bits, o, t, ne);
         }
-        if (!grid_sync(a.bar)) break;
+        if (!grid_sync(bar)) break;
         int32_t *tq = qin; qin = qout; qout = tq;
         it++;
     }
@@ -166,10 +167,11 @@ void bfs_fused(Ctx &c, Graph &G, Workspace &ws, int32_t src, const gg_schedule &
     GG_CHECK_LAUNCH();
     fill_i32(c, ws.counters.p, 1, 1);  // |F0| = 1
     c.launches++;
+    const int blocks = fused_grid(kern, 2, c.num_cus);
     FusedBfsArgs a{g, depth, ws.q[0].p, ws.q[1].p, ws.counters.p, ws.boolmap[0].p, ws.bitmap[0].p,
-                   s.threshold, prepare_barrier(c, ws), c.edge_counter};
+                   s.threshold, prepare_barrier(c, ws, blocks), c.edge_counter};
     void *args[] = {&a};
-    launch_cooperative(c, kern, fused_grid(kern, 2, c.num_cus), args);
+    launch_cooperative(c, kern, blocks, args);
     check_barrier(c, ws);
     GG_HIP(hipMemcpyAsync(ws.h_i32.p, ws.counters.p, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
     GG_HIP(hipStreamSynchronize(c.s));

@@ -1,0 +1,151 @@
+// Connected components by hooking and shortcutting (the Soman et al.
+// algorithm the paper's Evaluation section names for CC). Each round sweeps
+// every edge (u, v) with the schedule's load balancer: when the labels of
+// the endpoints differ, the larger label's entry is lowered to the smaller
+// one with an atomic min (hooking); then every label is replaced by the root
+// it reaches (shortcutting). Rounds repeat until a sweep hooks nothing. Labels
+// only decrease and never leave the component, so the fixpoint labels every
+// vertex with the smallest id of its component.
+#include "algos.hpp"
+#include "driver.hpp"
+#include "fused.hpp"
+
+namespace gg {
+
+struct CcHook {
+    int32_t *label;
+    int32_t *changed;
+    __device__ __forceinline__ bool active(int) const { return true; }
+    __device__ __forceinline__ bool done(int) const { return false; }
+    __device__ __forceinline__ int edge(int u, int v, int) const {
+        if (v < u) return -1;  // symmetric graph: every undirected edge once
+        const int lu = label[u], lv = label[v];
+        if (lu != lv) {
+            const int hi = lu > lv ? lu : lv, lo = lu > lv ? lv : lu;
+            if (atomic_min_i32(&label[hi], lo) > lo) *changed = 1;
+        }
+        return -1;
+    }
+};
+
+__global__ __launch_bounds__(kBlock) void k_cc_init(int32_t *label, int32_t *ids, int n) {
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
+        label[v] = v;
+        ids[v] = v;
+    }
+}
+
+__device__ __forceinline__ void cc_compress_dev(int32_t *label, int n, Tid t) {
+    for (int v = t.block * kBlock + (int)threadIdx.x; v < n; v += t.nblocks * kBlock) {
+        int l = label[v];
+        for (;;) {
+            const int ll = label[l];
+            if (ll == l) break;
+            l = ll;
+        }
+        label[v] = l;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cc_compress(int32_t *label, int n) {
+    cc_compress_dev(label, n, Tid::here());
+}
+
+// ---- fused: hook / barrier / shortcut / barrier in one persistent launch ----
+struct FusedCcArgs {
+    DevGraph g;
+    int32_t *label;
+    int32_t *ids;
+    int32_t *ctr;  // [0..2] changed flags (rotating), [3] rounds
+    GridBarrier bar;
+    unsigned long long *ecount;
+};
+
+template <int LB>
+__global__ __launch_bounds__(kBlock) void k_cc_fused(FusedCcArgs a) {
+    const Tid t = Tid::here();
+    long long ne = 0;
+    GridBarrier bar = a.bar;
+    const SrcQueue src{a.ids, a.g.n};
+    OutFrontier o{};  // hooks emit nothing
+    int r = 0;
+    for (;;) {
+        // round r hooks into flag r%3 and everyone reads it after the second
+        // barrier; flag (r+1)%3 was last read before round r-1's barriers
+        int32_t *changed = a.ctr + (r % 3);
+        if (t.block == 0 && threadIdx.x == 0)
+            __hip_atomic_store(a.ctr + ((r + 1) % 3), 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        CcHook f{a.label, changed};
+        if constexpr (LB == GG_LB_VERTEX_BASED) lb_vp<kCreateBoolmap, kDedupNone>(a.g, src, f, o, t, ne);
+        else if constexpr (LB == GG_LB_WM) lb_wm<kCreateBoolmap, kDedupNone>(a.g, src, f, o, t, ne);
+        else if constexpr (LB == GG_LB_CM) lb_cm<kCreateBoolmap, kDedupNone>(a.g, src, f, o, t, ne);
+        else lb_etwc<kCreateBoolmap, kDedupNone>(a.g, src, f, o, t, ne);
+        if (!grid_sync(bar)) break;
+        cc_compress_dev(a.label, a.g.n, t);
+        if (!grid_sync(bar)) break;
+        r++;
+        if (load_relaxed(changed) == 0) break;
+    }
+    if (t.block == 0 && threadIdx.x == 0) a.ctr[3] = r;
+    flush_edge_count(ne, a.ecount);
+}
+
+void cc_run(Graph &G, const gg_schedule &sch, int32_t *label, hipStream_t stream, gg_stats *st) {
+    Ctx c;
+    c.s = stream;
+    c.num_cus = G.num_cus;
+    StatsScope scope(st, c);
+    Lease ws(G);
+    const gg_simple_schedule &s = sch.s1;
+    if (s.load_balance == GG_LB_EDGE_ONLY) ensure_coo(c, G);
+    const DevGraph g = G.view();
+    const int n = g.n;
+    ws->aux_i32[0].ensure(n);  // identity frontier: every vertex is a source each round
+    ws->counters.ensure(64);
+    ws->h_i32.ensure(16);
+    fill_i32(c, ws->counters.p, 64, 0);
+    hipLaunchKernelGGL(k_cc_init, dim3(blocks_for(n, kBlock, 8192)), dim3(kBlock), 0, c.s, label,
+                       ws->aux_i32[0].p, n);
+    GG_CHECK_LAUNCH();
+    c.launches++;
+    if (s.kernel_fusion) {
+        const void *kern = nullptr;
+        switch (s.load_balance) {
+        case GG_LB_VERTEX_BASED: kern = (const void *)k_cc_fused<GG_LB_VERTEX_BASED>; break;
+        case GG_LB_WM: kern = (const void *)k_cc_fused<GG_LB_WM>; break;
+        case GG_LB_CM: kern = (const void *)k_cc_fused<GG_LB_CM>; break;
+        case GG_LB_ETWC: kern = (const void *)k_cc_fused<GG_LB_ETWC>; break;
+        default: throw Error(GG_ERR_UNSUPPORTED_SCHEDULE, "kernel fusion supports VERTEX_BASED, WM, CM and ETWC");
+        }
+        const int blocks = fused_grid(kern, 2, c.num_cus);
+        FusedCcArgs a{g, label, ws->aux_i32[0].p, ws->counters.p, prepare_barrier(c, *ws, blocks), c.edge_counter};
+        void *args[] = {&a};
+        launch_cooperative(c, kern, blocks, args);
+        check_barrier(c, *ws);
+        if (st) {
+            st->fused = 1;
+            st->iterations = read_i32(c, ws->counters.p + 3, ws->h_i32.p);
+            st->push_iterations = st->iterations;
+        }
+        scope.finish();
+        return;
+    }
+    // the hooks emit nothing: a dense output map receives no writes
+    ws->boolmap[0].ensure(((size_t)n + 255) / 256 * 256);
+    OutFrontier o{};
+    o.boolmap = ws->boolmap[0].p;
+    const PushPlan p{s.load_balance, kCreateBoolmap, kDedupNone};
+    for (;;) {
+        fill_i32(c, ws->counters.p, 1, 0);
+        push_apply(c, g, *ws, p, ws->aux_i32[0].p, n, CcHook{label, ws->counters.p}, o,
+                   member_map(*ws, n, s.load_balance));
+        hipLaunchKernelGGL(k_cc_compress, dim3(blocks_for(n, kBlock, 8192)), dim3(kBlock), 0, c.s, label, n);
+        GG_CHECK_LAUNCH();
+        c.launches++;
+        if (st) { st->iterations++; st->push_iterations++; st->vertices_processed += n; }
+        if (read_i32(c, ws->counters.p, ws->h_i32.p) == 0) break;
+    }
+    scope.finish();
+}
+
+}  // namespace gg

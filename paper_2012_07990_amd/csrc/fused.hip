@@ -17,15 +17,15 @@ void launch_cooperative(Ctx &c, const void *kernel, int blocks, void **args) {
     c.launches++;
 }
 
-GridBarrier prepare_barrier(Ctx &c, Workspace &ws) {
-    ws.barrier.ensure(4);
-    fill_i32(c, reinterpret_cast<int32_t *>(ws.barrier.p), 4, 0);
-    return GridBarrier{ws.barrier.p, ws.barrier.p + 1, ws.barrier.p + 2};
+GridBarrier prepare_barrier(Ctx &c, Workspace &ws, int blocks) {
+    ws.barrier.ensure((size_t)blocks + 4);
+    fill_i32(c, reinterpret_cast<int32_t *>(ws.barrier.p), blocks + 4, 0);
+    return GridBarrier{ws.barrier.p + 4, ws.barrier.p + 1, ws.barrier.p + 2, 0u};
 }
 
 void check_barrier(Ctx &c, Workspace &ws) {
     unsigned v[4];
-    GG_HIP(hipMemcpyAsync(v, ws.barrier.p, sizeof(v), hipMemcpyDeviceToHost, c.s));
+    GG_HIP(hipMemcpyAsync(v, ws.barrier.p, sizeof(v), hipMemcpyDeviceToHost, c.s));  // {-, release, abort, -}
     GG_HIP(hipStreamSynchronize(c.s));
     require(v[2] == 0, GG_ERR_DEVICE, "fused kernel aborted: a grid barrier wait exceeded its limit");
 }

@@ -17,39 +17,65 @@
 namespace gg {
 
 struct GridBarrier {
-    unsigned *count;   // arrivals in the current phase
-    unsigned *gen;     // phase number
-    unsigned *abort;   // set when a wait exceeded the spin limit
+    unsigned *arrive;   // [gridDim.x] last barrier epoch each workgroup reached
+    unsigned *release;  // last epoch released by workgroup 0
+    unsigned *abort;    // set when a wait exceeded the spin limit
+    unsigned epoch;     // barriers passed so far (kept per lane, equal grid-wide)
 };
 
-constexpr long long kBarrierSpinLimit = 1ll << 25;  // ~seconds with s_sleep backoff
+constexpr long long kBarrierSpinLimit = 1ll << 24;  // ~seconds with s_sleep backoff
 
-// Returns false when the barrier was aborted (the caller must then leave).
-__device__ __forceinline__ bool grid_sync(const GridBarrier &b) {
+__device__ __forceinline__ unsigned ld_agent(const unsigned *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(unsigned *p, unsigned v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Flag barrier: every workgroup publishes its arrival in its own word (no
+// contended atomic), workgroup 0 polls all words in parallel and then
+// publishes the release epoch that the others poll. One agent-scope release
+// fence before arriving and one acquire fence after leaving; the polls are
+// relaxed. Returns false when the barrier was aborted (the caller leaves).
+__device__ __forceinline__ bool grid_sync(GridBarrier &b) {
     __shared__ unsigned s_abort;
+    const unsigned ep = ++b.epoch;
     __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned nblocks = gridDim.x;
-        const unsigned g = __hip_atomic_load(b.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned arrived = __hip_atomic_fetch_add(b.count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == nblocks - 1) {
-            __hip_atomic_store(b.count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(b.gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        st_agent(&b.arrive[blockIdx.x], ep);
+        s_abort = 0;
+    }
+    if (blockIdx.x == 0) {
+        __syncthreads();
+        bool bad = false;
+        for (unsigned i = threadIdx.x; i < gridDim.x; i += blockDim.x) {
             long long spins = 0;
-            while (__hip_atomic_load(b.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+            while (ld_agent(&b.arrive[i]) < ep) {
                 __builtin_amdgcn_s_sleep(1);
-                if (++spins > kBarrierSpinLimit) {
-                    __hip_atomic_store(b.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (++spins > kBarrierSpinLimit || ((spins & 255) == 0 && ld_agent(b.abort))) {
+                    bad = true;
                     break;
                 }
-                if ((spins & 1023) == 0 &&
-                    __hip_atomic_load(b.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                    break;
+            }
+            if (bad) break;
+        }
+        if (bad) { st_agent(b.abort, 1u); s_abort = 1; }
+        __syncthreads();
+        if (threadIdx.x == 0) st_agent(b.release, ep);
+    } else if (threadIdx.x == 0) {
+        long long spins = 0;
+        while (ld_agent(b.release) < ep) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > kBarrierSpinLimit || ((spins & 255) == 0 && ld_agent(b.abort))) {
+                st_agent(b.abort, 1u);
+                break;
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
-        s_abort = __hip_atomic_load(b.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (ld_agent(b.abort)) s_abort = 1;
     }
     __syncthreads();
     return s_abort == 0;
@@ -63,8 +89,8 @@ int fused_grid(const void *kernel, int per_cu, int num_cus);
 // co-resident).
 void launch_cooperative(Ctx &c, const void *kernel, int blocks, void **args);
 
-// Allocate/zero the barrier words {count, gen, abort} in the workspace.
-GridBarrier prepare_barrier(Ctx &c, Workspace &ws);
+// Allocate/zero the barrier words in the workspace for a grid of `blocks`.
+GridBarrier prepare_barrier(Ctx &c, Workspace &ws, int blocks);
 // Read the abort flag after the kernel; throws if the loop was aborted.
 void check_barrier(Ctx &c, Workspace &ws);
 

@@ -305,6 +305,25 @@ __device__ __forceinline__ int upper_bound_ll(const long long *a, int n, long lo
     return lo;
 }
 
+// Last index i in [0, n) with a[i] <= x (a ascending, a[0] <= x), found by a
+// whole wavefront: each round the 64 lanes probe 64 evenly spaced positions
+// and a ballot keeps the last one that qualifies (log_64 n dependent loads).
+__device__ __forceinline__ int wave_last_le(const long long *a, int n, long long x) {
+    const int lane = lane_id();
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int step = (hi - lo + kWave - 1) / kWave;
+        const int p = lo + lane * step;
+        const bool ok = p < hi && a[p] <= x;
+        const uint64_t m = __ballot(ok);
+        const int hl = 63 - __builtin_clzll(m);
+        const int nlo = lo + hl * step;
+        hi = min(hi, nlo + step);
+        lo = nlo;
+    }
+    return lo;
+}
+
 template <int CREATE, int DEDUP, class Src, class F>
 __device__ void lb_strict(const DevGraph &g, const Src &src, const long long *scan, F &f,
                           const OutFrontier &out, Tid t, long long &ne) {
@@ -315,9 +334,13 @@ __device__ void lb_strict(const DevGraph &g, const Src &src, const long long *sc
     const long long nchunks = (total + W - 1) / W;
     for (long long c = t.block; c < nchunks; c += t.nblocks) {
         const long long r0 = c * W, r1 = (r0 + W < total) ? r0 + W : total;
-        if (threadIdx.x == 0) {
-            s_k0 = upper_bound_ll(scan, src.size + 1, r0) - 1;      // owner of r0
-            s_k1 = upper_bound_ll(scan, src.size + 1, r1 - 1) - 1;  // owner of r1-1
+        // owners of r0 and r1-1 (waves 0 and 1 search in parallel)
+        if (threadIdx.x < kWave) {
+            const int k = wave_last_le(scan, src.size + 1, r0);
+            if (threadIdx.x == 0) s_k0 = k;
+        } else if (threadIdx.x < 2 * kWave) {
+            const int k = wave_last_le(scan, src.size + 1, r1 - 1);
+            if (threadIdx.x == kWave) s_k1 = k;
         }
         __syncthreads();
         const int k0 = s_k0, k1 = s_k1;

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <map>
+#include <utility>
 #include <memory>
 #include <mutex>
 #include <vector>
@@ -18,6 +19,47 @@ struct Ctx {
     int launches = 0;
     unsigned long long *edge_counter = nullptr;  // device, null unless counting
     int num_cus = 256;
+};
+
+// Event timing of one kernel's launches (GG_STATS_TIME_KERNELS).
+struct KernelTimer {
+    bool on = false;
+    hipStream_t s = nullptr;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    void begin() {
+        if (!on) return;
+        hipEvent_t a, b;
+        GG_HIP(hipEventCreate(&a));
+        GG_HIP(hipEventCreate(&b));
+        ev.emplace_back(a, b);
+        GG_HIP(hipEventRecord(a, s));
+    }
+    void end() {
+        if (!on) return;
+        GG_HIP(hipEventRecord(ev.back().second, s));
+    }
+    // total milliseconds (synchronises); releases the events
+    double total() {
+        double t = 0;
+        for (auto &p : ev) {
+            GG_HIP(hipEventSynchronize(p.second));
+            float ms = 0;
+            GG_HIP(hipEventElapsedTime(&ms, p.first, p.second));
+            t += ms;
+        }
+        for (auto &p : ev) {
+            (void)hipEventDestroy(p.first);
+            (void)hipEventDestroy(p.second);
+        }
+        ev.clear();
+        return t;
+    }
+    ~KernelTimer() {
+        for (auto &p : ev) {
+            (void)hipEventDestroy(p.first);
+            (void)hipEventDestroy(p.second);
+        }
+    }
 };
 
 // ---- device buffers ------------------------------------------------------------------
@@ -106,6 +148,8 @@ struct Graph {
     DevBuf<uint32_t> w;
     int32_t max_degree = 0;
     std::map<int32_t, std::unique_ptr<EdgeBlocked>> eb;  // per blocking size
+    DevBuf<int32_t> chunk_rows;  // STRICT pull: owner rows of each edge chunk's first/last edge
+    long long chunk_rows_chunks = -1;
     std::mutex mu;
     std::vector<std::unique_ptr<Workspace>> pool;
     int device = 0;

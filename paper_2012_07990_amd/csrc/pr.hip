@@ -23,6 +23,7 @@
 // ~1e-5 absolute). Every PULL form is deterministic; the PUSH forms use FP64
 // atomic adds, whose order varies.
 #include <algorithm>
+#include <cstdio>
 
 #include "algos.hpp"
 #include "lb.hpp"
@@ -209,11 +210,31 @@ __global__ __launch_bounds__(kBlock) void k_pr_pull_etwc(PrArgs a) {
     pr_finish(a, dl);
 }
 
+// owner row of edge e: the last r with row_ptr[r] <= e
+__device__ __forceinline__ int owner_row(const int32_t *rp, int n, long long e) {
+    int lo = 0, hi = n;  // rp[lo] <= e < rp[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (rp[mid] <= e) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// once per graph: rows[2c] = owner of chunk c's first edge, rows[2c+1] = owner
+// of its last edge
+__global__ __launch_bounds__(kBlock) void k_pr_partition(DevGraph g, long long nchunks, int32_t *rows) {
+    for (long long c = (long long)blockIdx.x * kBlock + threadIdx.x; c < nchunks; c += (long long)gridDim.x * kBlock) {
+        const long long E0 = c * kPrChunk, E1 = (E0 + kPrChunk < g.m) ? E0 + kPrChunk : g.m;
+        rows[2 * c] = owner_row(g.row_ptr, g.n, E0);
+        rows[2 * c + 1] = owner_row(g.row_ptr, g.n, E1 - 1);
+    }
+}
+
 // STRICT: chunk c holds edges [c*C, c*C + C). Rows entirely inside a chunk
 // get their sum written to acc; the chunk's first and last rows also leave
 // their in-chunk partial sums in head[c] / tail[c].
-__global__ __launch_bounds__(kBlock) void k_pr_strict_chunks(PrArgs a, double *acc, double *head, double *tail,
-                                                             long long nchunks) {
+__global__ __launch_bounds__(kBlock) void k_pr_strict_chunks(PrArgs a, const int32_t *chunk_rows, double *acc,
+                                                             double *head, double *tail, long long nchunks) {
     __shared__ float vals[kPrChunk];
     __shared__ int s_r0, s_r1;
     __shared__ int long_r[kPrChunk / 32 + 1];
@@ -228,13 +249,8 @@ __global__ __launch_bounds__(kBlock) void k_pr_strict_chunks(PrArgs a, double *a
             if (e < E1) vals[e - E0] = a.contrib_in[a.g.col[e]];
         }
         if (tid == 0) {
-            // owners of E0 and E1-1: last row r with row_ptr[r] <= e
-            int lo = 0, hi = a.g.n;  // row_ptr[lo] <= E0 < row_ptr[hi]
-            while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (a.g.row_ptr[mid] <= E0) lo = mid; else hi = mid; }
-            s_r0 = lo;
-            lo = s_r0; hi = a.g.n;
-            while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (a.g.row_ptr[mid] <= E1 - 1) lo = mid; else hi = mid; }
-            s_r1 = lo;
+            s_r0 = chunk_rows[2 * c];
+            s_r1 = chunk_rows[2 * c + 1];
             n_long = 0;
         }
         __syncthreads();
@@ -342,8 +358,24 @@ void pr_run(Graph &G, const gg_schedule &sch, float damping, int iters, uint32_t
     if (strict) {
         ws->pr_head.ensure((size_t)std::max(nchunks, 1ll));
         ws->pr_tail.ensure((size_t)std::max(nchunks, 1ll));
+        std::lock_guard<std::mutex> lk(G.mu);
+        if (G.chunk_rows_chunks != nchunks) {
+            G.chunk_rows.ensure((size_t)std::max(2 * nchunks, 2ll));
+            if (nchunks > 0) {
+                hipLaunchKernelGGL(k_pr_partition, dim3(blocks_for(nchunks, kBlock, 4096)), dim3(kBlock), 0, c.s, g,
+                                   nchunks, G.chunk_rows.p);
+                GG_CHECK_LAUNCH();
+                c.launches++;
+            }
+            G.chunk_rows_chunks = nchunks;
+        }
     }
     fill_i32(c, reinterpret_cast<int32_t *>(ws->pr_done.p), 1, 0);
+    KernelTimer kt;
+    kt.on = st && (st->flags & GG_STATS_TIME_KERNELS);
+    kt.s = c.s;
+    const char *kname = push ? "k_pr_push_edges" : strict ? "k_pr_strict_chunks"
+                        : lb == GG_LB_WM ? "k_pr_pull_wm" : lb == GG_LB_ETWC ? "k_pr_pull_etwc" : "k_pr_pull_vp";
     GG_HIP(hipEventRecord(e0, c.s));
 
     PrArgs a{};
@@ -373,32 +405,45 @@ void pr_run(Graph &G, const gg_schedule &sch, float damping, int iters, uint32_t
                 for (size_t sg = 0; sg + 1 < eb->seg_start.size(); sg++) {
                     const long long lo = eb->seg_start[sg], hi = eb->seg_start[sg + 1];
                     if (hi <= lo) continue;
+                    kt.begin();
                     hipLaunchKernelGGL(k_pr_push_edges, dim3(blocks_for(hi - lo, kBlock, 16384)), dim3(kBlock), 0,
                                        c.s, eb->src.p, eb->dst.p, lo, hi, a.contrib_in, a.acc);
+                    kt.end();
                     GG_CHECK_LAUNCH();
                     c.launches++;
                 }
             } else if (g.m > 0) {
+                kt.begin();
                 hipLaunchKernelGGL(k_pr_push_edges, dim3(blocks_for(g.m, kBlock, 16384)), dim3(kBlock), 0, c.s,
                                    g.coo_src, g.col, 0ll, (long long)g.m, a.contrib_in, a.acc);
+                kt.end();
                 GG_CHECK_LAUNCH();
                 c.launches++;
             }
             hipLaunchKernelGGL(k_pr_apply, dim3(nblk), dim3(kBlock), 0, c.s, a, 1);
         } else if (strict) {
             if (nchunks > 0) {
+                kt.begin();
                 hipLaunchKernelGGL(k_pr_strict_chunks, dim3((unsigned)std::min<long long>(nchunks, 65535)),
-                                   dim3(kBlock), 0, c.s, a, ws->pr_acc.p, ws->pr_head.p, ws->pr_tail.p, nchunks);
+                                   dim3(kBlock), 0, c.s, a, G.chunk_rows.p, ws->pr_acc.p, ws->pr_head.p,
+                                   ws->pr_tail.p, nchunks);
+                kt.end();
                 GG_CHECK_LAUNCH();
                 c.launches++;
             }
             hipLaunchKernelGGL(k_pr_apply, dim3(nblk), dim3(kBlock), 0, c.s, a, 0);
         } else if (lb == GG_LB_WM) {
+            kt.begin();
             hipLaunchKernelGGL(k_pr_pull_wm, dim3(nblk_wm), dim3(kBlock), 0, c.s, a);
+            kt.end();
         } else if (lb == GG_LB_ETWC) {
+            kt.begin();
             hipLaunchKernelGGL(k_pr_pull_etwc, dim3(nblk), dim3(kBlock), 0, c.s, a);
+            kt.end();
         } else {
+            kt.begin();
             hipLaunchKernelGGL(k_pr_pull_vp, dim3(nblk), dim3(kBlock), 0, c.s, a);
+            kt.end();
         }
         GG_CHECK_LAUNCH();
         c.launches++;
@@ -419,6 +464,11 @@ void pr_run(Graph &G, const gg_schedule &sch, float damping, int iters, uint32_t
             st->vertices_processed = (int64_t)n * iters;
         }
         if (push) st->push_iterations = iters; else st->pull_iterations = iters;
+        if (kt.on) {
+            st->kernel_launches = (int32_t)kt.ev.size();
+            st->kernel_ms = kt.total();
+            snprintf(st->kernel_name, sizeof(st->kernel_name), "%s", kname);
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

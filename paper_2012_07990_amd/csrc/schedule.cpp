@@ -128,7 +128,7 @@ void validate_schedule(const Graph &g, int algo, const gg_schedule &s) {
     if (s.hybrid) {
         if (!(s.threshold > 0.f && s.threshold <= 1.f)) throw Error(GG_ERR_INVALID_ARG, "threshold must be in (0, 1]");
         check_simple(g, algo, s.s2, true);
-        if (algo == GG_ALGO_PR || algo == GG_ALGO_CC) bad("hybrid schedules apply to frontier-driven loops (BFS, BC, SSSP)");
+        if (algo != GG_ALGO_BFS && algo != GG_ALGO_BC) bad("hybrid (push/pull) schedules apply to BFS and BC");
         if (s.s1.kernel_fusion && s.s2.direction == GG_PUSH && s.s2.load_balance != s.s1.load_balance)
             bad("a fused hybrid loop pushes with s1's load balancer");
         if (s.s1.kernel_fusion && algo != GG_ALGO_BFS) bad("fused hybrid loops are available for BFS");
