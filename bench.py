@@ -80,6 +80,9 @@ def sweep_schedules(gg):
     out["pr"]["push-edge"] = gg.make_schedule(lb="edge_only")
     for N in [1 << 18, 1 << 20, 1 << 22]:
         out["pr"]["push-eb-%d" % N] = gg.make_schedule(lb="edge_only", edge_blocking=True, blocking_size=N)
+    for N in [1 << 17, 1 << 18, 1 << 19, 1 << 20, 1 << 21]:
+        out["pr"]["pull-strict-eb-%d" % N] = gg.make_schedule(lb="strict", direction=gg.PULL, edge_blocking=True,
+                                                              blocking_size=N)
     for lb in ["vp", "etwc"]:
         out["bc"]["push-" + lb] = gg.make_schedule(lb=lb)
     for th in [0.001, 0.01, 0.05]:

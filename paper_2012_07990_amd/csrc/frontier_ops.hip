@@ -301,3 +301,61 @@ void ensure_coo(Ctx &c, Graph &G) {
 }
 
 }  // namespace gg
+
+namespace gg {
+
+// ---- generic in-place exclusive scan of int32 counts: data[0..n) counts ->
+// data[0..n] offsets (data[n] = total). Totals must fit in int32.
+__global__ __launch_bounds__(kBlock) void k_iscan_reduce(const int32_t *data, int n, long long *partials) {
+    __shared__ long long s_tmp[kBlock / kWave];
+    const long long base = (long long)blockIdx.x * kScanTile;
+    long long s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        const long long i = base + (long long)k * kBlock + threadIdx.x;
+        if (i < n) s += data[i];
+    }
+    s = block_sum_ll(s, s_tmp);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_iscan_apply(int32_t *data, int n, const long long *partials) {
+    __shared__ long long s_w[kBlock / kWave];
+    const long long base = (long long)blockIdx.x * kScanTile;
+    const long long first = base + (long long)threadIdx.x * kScanItems;
+    long long vals[kScanItems];
+    long long s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        const long long i = first + k;
+        vals[k] = i < n ? data[i] : 0;
+        s += vals[k];
+    }
+    const long long incl = wave_incl_scan64(s);
+    if (lane_id() == kWave - 1) s_w[threadIdx.x / kWave] = incl;
+    __syncthreads();
+    long long off = partials[blockIdx.x];
+    for (int w = 0; w < (int)(threadIdx.x / kWave); w++) off += s_w[w];
+    long long run = off + incl - s;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        const long long i = first + k;
+        if (i <= n) data[i] = (int32_t)run;
+        run += vals[k];
+    }
+}
+
+void exclusive_scan_i32(Ctx &c, int32_t *data, int n, long long *partials) {
+    const int tiles = (n + 1 + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_iscan_reduce, dim3(tiles), dim3(kBlock), 0, c.s, data, n, partials);
+    GG_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, c.s, partials, tiles);
+    GG_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_iscan_apply, dim3(tiles), dim3(kBlock), 0, c.s, data, n, partials);
+    GG_CHECK_LAUNCH();
+    c.launches += 3;
+}
+
+size_t exclusive_scan_partials(int n) { return (size_t)(n + 1 + kScanTile - 1) / kScanTile + 1; }
+
+}  // namespace gg

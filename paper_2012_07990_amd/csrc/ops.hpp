@@ -139,6 +139,19 @@ struct EdgeBlocked {
     int32_t seg_vertices = 0;
 };
 
+// PULL EdgeBlocking: the CSR split by source segment [s*N, (s+1)*N); each
+// segment is a CSR over all destinations (rows keep their ascending order).
+struct PullBlocked {
+    int32_t N = 0;
+    int S = 0;
+    DevBuf<int32_t> rp;    // S x (n+1) row offsets (unused when S == 1)
+    DevBuf<int32_t> col;   // m sources, segment-major (unused when S == 1)
+    const int32_t *rp_ptr = nullptr, *col_ptr = nullptr;  // the layout in use
+    std::vector<long long> m_s, col_base;
+    DevBuf<int32_t> chunk_rows;            // per segment: owner rows of each chunk's first/last edge
+    std::vector<long long> chunk_base, nchunks;
+};
+
 struct Graph {
     int32_t n = 0;
     int64_t m = 0;
@@ -148,8 +161,7 @@ struct Graph {
     DevBuf<uint32_t> w;
     int32_t max_degree = 0;
     std::map<int32_t, std::unique_ptr<EdgeBlocked>> eb;  // per blocking size
-    DevBuf<int32_t> chunk_rows;  // STRICT pull: owner rows of each edge chunk's first/last edge
-    long long chunk_rows_chunks = -1;
+    std::map<int32_t, std::unique_ptr<PullBlocked>> pull_eb;  // STRICT pull partitions per segment width
     std::mutex mu;
     std::vector<std::unique_ptr<Workspace>> pool;
     int device = 0;
@@ -194,6 +206,9 @@ void count_bitmap(Ctx &c, const unsigned long long *map, int n, int32_t *count);
 void degree_scan(Ctx &c, const DevGraph &g, const int32_t *q, int count, long long *scan,
                  long long *partials);
 size_t degree_scan_partials(int count);
+// in place: data[0..n) counts -> data[0..n] exclusive offsets (int32 totals)
+void exclusive_scan_i32(Ctx &c, int32_t *data, int n, long long *partials);
+size_t exclusive_scan_partials(int n);
 
 // device -> pinned host readback of one int, then stream sync
 int32_t read_i32(Ctx &c, const int32_t *dev, int32_t *pinned);

@@ -44,7 +44,6 @@ struct PrArgs {
     unsigned *done;         // last-block ticket
     int dangling;           // 0: drop the dangling mass
     double *acc;            // STRICT / PUSH accumulators (reset after read)
-    const double *head, *tail;  // STRICT chunk partials
 };
 
 __device__ __forceinline__ double pr_base(const PrArgs &a) {
@@ -222,31 +221,34 @@ __device__ __forceinline__ int owner_row(const int32_t *rp, int n, long long e) 
 
 // once per graph: rows[2c] = owner of chunk c's first edge, rows[2c+1] = owner
 // of its last edge
-__global__ __launch_bounds__(kBlock) void k_pr_partition(DevGraph g, long long nchunks, int32_t *rows) {
+__global__ __launch_bounds__(kBlock) void k_pr_partition(const int32_t *rp, int n, long long m, long long nchunks,
+                                                         int32_t *rows) {
     for (long long c = (long long)blockIdx.x * kBlock + threadIdx.x; c < nchunks; c += (long long)gridDim.x * kBlock) {
-        const long long E0 = c * kPrChunk, E1 = (E0 + kPrChunk < g.m) ? E0 + kPrChunk : g.m;
-        rows[2 * c] = owner_row(g.row_ptr, g.n, E0);
-        rows[2 * c + 1] = owner_row(g.row_ptr, g.n, E1 - 1);
+        const long long E0 = c * kPrChunk, E1 = (E0 + kPrChunk < m) ? E0 + kPrChunk : m;
+        rows[2 * c] = owner_row(rp, n, E0);
+        rows[2 * c + 1] = owner_row(rp, n, E1 - 1);
     }
 }
 
-// STRICT: chunk c holds edges [c*C, c*C + C). Rows entirely inside a chunk
-// get their sum written to acc; the chunk's first and last rows also leave
-// their in-chunk partial sums in head[c] / tail[c].
-__global__ __launch_bounds__(kBlock) void k_pr_strict_chunks(PrArgs a, const int32_t *chunk_rows, double *acc,
-                                                             double *head, double *tail, long long nchunks) {
+// STRICT: chunk c holds edges [c*C, c*C + C) of a (segment) CSR. Rows
+// entirely inside a chunk add their sum to accum; the chunk's first and last
+// rows also leave their in-chunk partial sums in head[c] / tail[c], which
+// k_pr_fixup adds for the rows that span chunks.
+__global__ __launch_bounds__(kBlock) void k_pr_strict_chunks(const int32_t *rp, const int32_t *col, long long m,
+                                                             const float *contrib, const int32_t *chunk_rows,
+                                                             double *accum, double *head, double *tail,
+                                                             long long nchunks) {
     __shared__ float vals[kPrChunk];
     __shared__ int s_r0, s_r1;
     __shared__ int long_r[kPrChunk / 32 + 1];
     __shared__ int n_long;
     const int tid = threadIdx.x, lane = lane_id(), wib = tid / kWave;
-    const long long m = a.g.m;
     for (long long c = blockIdx.x; c < nchunks; c += gridDim.x) {
         const long long E0 = c * kPrChunk, E1 = (E0 + kPrChunk < m) ? E0 + kPrChunk : m;
 #pragma unroll
         for (int k = 0; k < kPrChunk / kBlock; k++) {
             const long long e = E0 + k * kBlock + tid;
-            if (e < E1) vals[e - E0] = a.contrib_in[a.g.col[e]];
+            if (e < E1) vals[e - E0] = contrib[col[e]];
         }
         if (tid == 0) {
             s_r0 = chunk_rows[2 * c];
@@ -257,60 +259,100 @@ __global__ __launch_bounds__(kBlock) void k_pr_strict_chunks(PrArgs a, const int
         const int r0 = s_r0, r1 = s_r1;
         // short rows (< 32 in-chunk edges): one lane each; long rows queued
         for (int r = r0 + tid; r <= r1; r += kBlock) {
-            const long long rb = a.g.row_ptr[r], re = a.g.row_ptr[r + 1];
+            const long long rb = rp[r], re = rp[r + 1];
             const int lo = (int)((rb > E0 ? rb : E0) - E0), hi = (int)((re < E1 ? re : E1) - E0);
             if (hi - lo >= 32) {
                 const int k = atomicAdd(&n_long, 1);
                 long_r[k] = r;
                 continue;
             }
-            double s = 0.0;
-            for (int i = lo; i < hi; i++) s += (double)vals[i];
-            if (rb >= E0 && re <= E1) acc[r] = s;
-            if (r == r0) head[c] = s;
-            if (r == r1) tail[c] = s;
+            double sum = 0.0;
+            for (int i = lo; i < hi; i++) sum += (double)vals[i];
+            if (rb >= E0 && re <= E1) { if (hi > lo) accum[r] += sum; }
+            if (r == r0) head[c] = sum;
+            if (r == r1) tail[c] = sum;
         }
         __syncthreads();
         for (int k = wib; k < n_long; k += kBlock / kWave) {
             const int r = long_r[k];
-            const long long rb = a.g.row_ptr[r], re = a.g.row_ptr[r + 1];
+            const long long rb = rp[r], re = rp[r + 1];
             const int lo = (int)((rb > E0 ? rb : E0) - E0), hi = (int)((re < E1 ? re : E1) - E0);
-            double s = 0.0;
-            for (int i = lo + lane; i < hi; i += kWave) s += (double)vals[i];
-            s = wave_sum(s);
+            double sum = 0.0;
+            for (int i = lo + lane; i < hi; i += kWave) sum += (double)vals[i];
+            sum = wave_sum(sum);
             if (lane == 0) {
-                if (rb >= E0 && re <= E1) acc[r] = s;
-                if (r == r0) head[c] = s;
-                if (r == r1) tail[c] = s;
+                if (rb >= E0 && re <= E1) accum[r] += sum;
+                if (r == r0) head[c] = sum;
+                if (r == r1) tail[c] = sum;
             }
         }
         __syncthreads();
     }
 }
 
-// Vertex apply after STRICT chunks (mode 0) or PUSH accumulation (mode 1).
-__global__ __launch_bounds__(kBlock) void k_pr_apply(PrArgs a, int mode) {
+// Rows that span chunks: a row that starts inside chunk c and ends beyond it
+// is chunk c's last row; its sum is tail[c] + the heads of the chunks it
+// covers, in chunk order.
+__global__ __launch_bounds__(kBlock) void k_pr_fixup(const int32_t *rp, long long m, const int32_t *chunk_rows,
+                                                     const double *head, const double *tail, double *accum,
+                                                     long long nchunks) {
+    for (long long c = (long long)blockIdx.x * kBlock + threadIdx.x; c < nchunks; c += (long long)gridDim.x * kBlock) {
+        const long long E0 = c * kPrChunk, E1 = (c + 1) * kPrChunk < m ? (c + 1) * kPrChunk : m;
+        const int r = chunk_rows[2 * c + 1];
+        const long long rb = rp[r], re = rp[r + 1];
+        if (re <= E1 || rb < E0) continue;  // fixed up by the chunk where the row starts
+        const long long c1 = (re - 1) / kPrChunk;
+        double sum = tail[c];
+        for (long long k = c + 1; k < c1; k++) sum += head[k];
+        sum += head[c1];
+        accum[r] += sum;
+    }
+}
+
+// Vertex apply after STRICT chunks or PUSH accumulation: reads the neighbour
+// sum from acc and resets it for the next round.
+__global__ __launch_bounds__(kBlock) void k_pr_apply(PrArgs a) {
     const double base = pr_base(a);
     double dl = 0;
     for (int v = blockIdx.x * kBlock + threadIdx.x; v < a.g.n; v += gridDim.x * kBlock) {
-        const int beg = a.g.row_ptr[v], end = a.g.row_ptr[v + 1];
-        double s = 0.0;
-        if (mode == 1) {
-            s = a.acc[v];
-            a.acc[v] = 0.0;
-        } else if (end > beg) {
-            const long long c0 = beg / kPrChunk, c1 = (end - 1) / kPrChunk;
-            if (c0 == c1) {
-                s = a.acc[v];
-            } else {
-                s = a.tail[c0];
-                for (long long c = c0 + 1; c < c1; c++) s += a.head[c];
-                s += a.head[c1];
-            }
-        }
-        pr_apply(a, v, base, s, end - beg, dl);
+        const int deg = a.g.row_ptr[v + 1] - a.g.row_ptr[v];
+        const double s = a.acc[v];
+        a.acc[v] = 0.0;
+        pr_apply(a, v, base, s, deg, dl);
     }
     pr_finish(a, dl);
+}
+
+// ---- PULL EdgeBlocking layout: segment s holds, for every destination row,
+// its sources in [s*N, (s+1)*N) (a contiguous piece of the sorted row).
+__device__ __forceinline__ int row_lower_bound(const int32_t *col, int lo, int hi, long long x) {
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (col[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_count(DevGraph g, int N, int S, int32_t *rp_s) {
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < g.n; v += gridDim.x * kBlock) {
+        const int beg = g.row_ptr[v], end = g.row_ptr[v + 1];
+        int lo = beg;
+        for (int s = 0; s < S; s++) {
+            const int hi = s == S - 1 ? end : row_lower_bound(g.col, lo, end, (long long)(s + 1) * N);
+            rp_s[(long long)s * (g.n + 1) + v] = hi - lo;
+            lo = hi;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_fill(DevGraph g, int N, int s, const int32_t *rp_s, int32_t *col_s) {
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < g.n; v += gridDim.x * kBlock) {
+        const int beg = g.row_ptr[v], end = g.row_ptr[v + 1];
+        const int lo = row_lower_bound(g.col, beg, end, (long long)s * N);
+        const int hi = row_lower_bound(g.col, lo, end, (long long)(s + 1) * N);
+        int32_t *dst = col_s + rp_s[v];
+        for (int e = lo; e < hi; e++) dst[e - lo] = g.col[e];
+    }
 }
 
 // PUSH EDGE_ONLY: acc[dst] += contrib[src] for every CSR entry
@@ -319,6 +361,71 @@ __global__ __launch_bounds__(kBlock) void k_pr_push_edges(const int32_t *src, co
     const long long stride = (long long)gridDim.x * kBlock;
     for (long long e = lo + (long long)blockIdx.x * kBlock + threadIdx.x; e < hi; e += stride)
         atomic_add_f64(&acc[dst[e]], (double)contrib[src[e]]);
+}
+
+// Build (once per graph and segment width) the STRICT pull layout: S = 1 uses
+// the graph's own CSR; S > 1 the source-segmented CSRs.
+static PullBlocked &pull_layout(Ctx &c, Graph &G, int N) {
+    const DevGraph g = G.view();
+    const int n = g.n;
+    const int S = (int)std::max<long long>(1, ((long long)n + N - 1) / N);
+    const int key = S == 1 ? 0 : N;
+    std::lock_guard<std::mutex> lk(G.mu);
+    auto it = G.pull_eb.find(key);
+    if (it != G.pull_eb.end()) return *it->second;
+    auto pb = std::make_unique<PullBlocked>();
+    pb->N = N;
+    pb->S = S;
+    if (S == 1) {
+        pb->rp_ptr = g.row_ptr;
+        pb->col_ptr = g.col;
+        pb->m_s = {(long long)g.m};
+        pb->col_base = {0};
+    } else {
+        pb->rp.ensure((size_t)S * (n + 1));
+        pb->col.ensure((size_t)std::max<long long>(g.m, 1));
+        hipLaunchKernelGGL(k_seg_count, dim3(blocks_for(n, kBlock, 16384)), dim3(kBlock), 0, c.s, g, N, S, pb->rp.p);
+        GG_CHECK_LAUNCH();
+        DevBuf<long long> part;
+        part.ensure(exclusive_scan_partials(n));
+        std::vector<int32_t> tot(S);
+        for (int s = 0; s < S; s++) {
+            exclusive_scan_i32(c, pb->rp.p + (size_t)s * (n + 1), n, part.p);
+            GG_HIP(hipMemcpyAsync(&tot[s], pb->rp.p + (size_t)s * (n + 1) + n, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                  c.s));
+        }
+        GG_HIP(hipStreamSynchronize(c.s));
+        long long base = 0;
+        for (int s = 0; s < S; s++) {
+            pb->m_s.push_back(tot[s]);
+            pb->col_base.push_back(base);
+            hipLaunchKernelGGL(k_seg_fill, dim3(blocks_for(n, kBlock, 16384)), dim3(kBlock), 0, c.s, g, N, s,
+                               pb->rp.p + (size_t)s * (n + 1), pb->col.p + base);
+            GG_CHECK_LAUNCH();
+            base += tot[s];
+        }
+        pb->rp_ptr = pb->rp.p;
+        pb->col_ptr = pb->col.p;
+    }
+    long long total_chunks = 0;
+    for (int s = 0; s < S; s++) {
+        pb->chunk_base.push_back(total_chunks);
+        const long long nc = (pb->m_s[s] + kPrChunk - 1) / kPrChunk;
+        pb->nchunks.push_back(nc);
+        total_chunks += nc;
+    }
+    pb->chunk_rows.ensure((size_t)std::max(2 * total_chunks, 2ll));
+    for (int s = 0; s < S; s++) {
+        if (pb->nchunks[s] == 0) continue;
+        hipLaunchKernelGGL(k_pr_partition, dim3(blocks_for(pb->nchunks[s], kBlock, 4096)), dim3(kBlock), 0, c.s,
+                           pb->rp_ptr + (S == 1 ? 0 : (size_t)s * (n + 1)), n, pb->m_s[s], pb->nchunks[s],
+                           pb->chunk_rows.p + 2 * pb->chunk_base[s]);
+        GG_CHECK_LAUNCH();
+    }
+    GG_HIP(hipStreamSynchronize(c.s));
+    auto &ref = *pb;
+    G.pull_eb[key] = std::move(pb);
+    return ref;
 }
 
 void ensure_coo(Ctx &c, Graph &G);
@@ -352,23 +459,15 @@ void pr_run(Graph &G, const gg_schedule &sch, float damping, int iters, uint32_t
     ws->pr_partial.ensure(apply_blocks + 1);
     ws->pr_dangling.ensure(2);
     ws->pr_done.ensure(1);
-    const long long nchunks = (g.m + kPrChunk - 1) / kPrChunk;
     const bool strict = !push && lb == GG_LB_STRICT;
+    PullBlocked *pb = nullptr;
     if (strict || push) ws->pr_acc.ensure(n);
     if (strict) {
-        ws->pr_head.ensure((size_t)std::max(nchunks, 1ll));
-        ws->pr_tail.ensure((size_t)std::max(nchunks, 1ll));
-        std::lock_guard<std::mutex> lk(G.mu);
-        if (G.chunk_rows_chunks != nchunks) {
-            G.chunk_rows.ensure((size_t)std::max(2 * nchunks, 2ll));
-            if (nchunks > 0) {
-                hipLaunchKernelGGL(k_pr_partition, dim3(blocks_for(nchunks, kBlock, 4096)), dim3(kBlock), 0, c.s, g,
-                                   nchunks, G.chunk_rows.p);
-                GG_CHECK_LAUNCH();
-                c.launches++;
-            }
-            G.chunk_rows_chunks = nchunks;
-        }
+        pb = &pull_layout(c, G, s.edge_blocking ? s.blocking_size : std::max(n, 1));
+        long long maxc = 1;
+        for (long long x : pb->nchunks) maxc = std::max(maxc, x);
+        ws->pr_head.ensure((size_t)maxc);
+        ws->pr_tail.ensure((size_t)maxc);
     }
     fill_i32(c, reinterpret_cast<int32_t *>(ws->pr_done.p), 1, 0);
     KernelTimer kt;
@@ -385,8 +484,6 @@ void pr_run(Graph &G, const gg_schedule &sch, float damping, int iters, uint32_t
     a.partials = ws->pr_partial.p;
     a.done = ws->pr_done.p;
     a.acc = (strict || push) ? ws->pr_acc.p : nullptr;
-    a.head = ws->pr_head.p;
-    a.tail = ws->pr_tail.p;
     // round 0
     a.contrib_out = ws->pr_contrib[0].p;
     a.rank_out = iters == 0 ? rank : nullptr;
@@ -420,18 +517,26 @@ void pr_run(Graph &G, const gg_schedule &sch, float damping, int iters, uint32_t
                 GG_CHECK_LAUNCH();
                 c.launches++;
             }
-            hipLaunchKernelGGL(k_pr_apply, dim3(nblk), dim3(kBlock), 0, c.s, a, 1);
+            hipLaunchKernelGGL(k_pr_apply, dim3(nblk), dim3(kBlock), 0, c.s, a);
         } else if (strict) {
-            if (nchunks > 0) {
+            for (int sg = 0; sg < pb->S; sg++) {
+                const long long nc = pb->nchunks[sg];
+                if (nc == 0) continue;
+                const int32_t *rp = pb->rp_ptr + (pb->S == 1 ? 0 : (size_t)sg * (n + 1));
+                const int32_t *cl = pb->col_ptr + pb->col_base[sg];
+                const int32_t *cr = pb->chunk_rows.p + 2 * pb->chunk_base[sg];
                 kt.begin();
-                hipLaunchKernelGGL(k_pr_strict_chunks, dim3((unsigned)std::min<long long>(nchunks, 65535)),
-                                   dim3(kBlock), 0, c.s, a, G.chunk_rows.p, ws->pr_acc.p, ws->pr_head.p,
-                                   ws->pr_tail.p, nchunks);
+                hipLaunchKernelGGL(k_pr_strict_chunks, dim3((unsigned)std::min<long long>(nc, 65535)), dim3(kBlock), 0,
+                                   c.s, rp, cl, pb->m_s[sg], a.contrib_in, cr, ws->pr_acc.p, ws->pr_head.p,
+                                   ws->pr_tail.p, nc);
                 kt.end();
                 GG_CHECK_LAUNCH();
-                c.launches++;
+                hipLaunchKernelGGL(k_pr_fixup, dim3(blocks_for(nc, kBlock, 4096)), dim3(kBlock), 0, c.s, rp,
+                                   pb->m_s[sg], cr, ws->pr_head.p, ws->pr_tail.p, ws->pr_acc.p, nc);
+                GG_CHECK_LAUNCH();
+                c.launches += 2;
             }
-            hipLaunchKernelGGL(k_pr_apply, dim3(nblk), dim3(kBlock), 0, c.s, a, 0);
+            hipLaunchKernelGGL(k_pr_apply, dim3(nblk), dim3(kBlock), 0, c.s, a);
         } else if (lb == GG_LB_WM) {
             kt.begin();
             hipLaunchKernelGGL(k_pr_pull_wm, dim3(nblk_wm), dim3(kBlock), 0, c.s, a);

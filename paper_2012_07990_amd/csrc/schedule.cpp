@@ -87,8 +87,11 @@ static void check_simple(const Graph &g, int algo, const gg_simple_schedule &s, 
     // processing algorithm's note): the topology-driven PageRank sweep.
     if (s.edge_blocking) {
         if (algo != GG_ALGO_PR) bad("EdgeBlocking applies only to all-edges operators (PageRank)");
-        if (s.load_balance != GG_LB_EDGE_ONLY || s.direction != GG_PUSH)
-            bad("EdgeBlocking needs EDGE_ONLY load balancing in the PUSH direction");
+        const bool push_eb = s.load_balance == GG_LB_EDGE_ONLY && s.direction == GG_PUSH;
+        const bool pull_eb = s.load_balance == GG_LB_STRICT && s.direction == GG_PULL;
+        if (!push_eb && !pull_eb)
+            bad("EdgeBlocking runs EDGE_ONLY in the PUSH direction (destination segments) or STRICT in the "
+                "PULL direction (source segments)");
     }
     switch (algo) {
     case GG_ALGO_BFS:

@@ -18,6 +18,9 @@ FORMS = {
     "push_edge": dict(lb="edge_only", direction=gg.PUSH),
     "push_eb_1k": dict(lb="edge_only", direction=gg.PUSH, edge_blocking=True, blocking_size=1000),
     "push_eb_64": dict(lb="edge_only", direction=gg.PUSH, edge_blocking=True, blocking_size=64),
+    "pull_strict_eb_1k": dict(lb="strict", direction=gg.PULL, edge_blocking=True, blocking_size=1000),
+    "pull_strict_eb_64": dict(lb="strict", direction=gg.PULL, edge_blocking=True, blocking_size=64),
+    "pull_strict_eb_big": dict(lb="strict", direction=gg.PULL, edge_blocking=True, blocking_size=1 << 20),
 }
 GRAPHS = ["rmat12", "rmat14", "grid64", "star5000", "cliques", "isolated7", "single", "path100k"]
 
@@ -57,7 +60,7 @@ def test_pr_iteration_counts(iters):
         check_pr(r, exp)
 
 
-@pytest.mark.parametrize("form", ["pull_vp", "pull_wm", "pull_etwc", "pull_strict"])
+@pytest.mark.parametrize("form", ["pull_vp", "pull_wm", "pull_etwc", "pull_strict", "pull_strict_eb_1k"])
 def test_pr_pull_deterministic(form):
     G = dev_graph("rmat14")
     a = G.pagerank(gg.make_schedule(**FORMS[form])).cpu().numpy()
@@ -83,7 +86,8 @@ def test_edgeblock_layout_matches_oracle(N, name):
 def test_pr_schedule_errors():
     G = dev_graph("rmat12")
     for kw in [dict(lb="cm", direction=gg.PULL), dict(lb="vp", direction=gg.PUSH),
-               dict(lb="vp", direction=gg.PULL, edge_blocking=True)]:
+               dict(lb="vp", direction=gg.PULL, edge_blocking=True),
+               dict(lb="strict", direction=gg.PUSH, edge_blocking=True)]:
         with pytest.raises(gg.GGError) as e:
             G.pagerank(gg.make_schedule(**kw))
         assert e.value.status == gg.ERR_UNSUPPORTED_SCHEDULE
