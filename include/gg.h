@@ -229,6 +229,19 @@ gg_status gg_bfs_multi(gg_graph *g, const int32_t *srcs_host, int32_t k, const g
 gg_status gg_bc_multi(gg_graph *g, const int32_t *srcs_host, int32_t k, const gg_schedule *s,
                       uint64_t *sigma_dev, float *delta_dev, gg_stream_t stream, gg_stats *stats);
 
+/*
+ * Autotuner (Auto-tuning subsection of the Compiler Implementation section):
+ * successive halving over the valid schedules of `algo` on g (load balancing,
+ * direction / hybrid threshold, frontier representation and creation,
+ * fusion, delta, EdgeBlocking width), timed on the probe sources (host array
+ * of nprobe ids; unused by CC and PR) within budget_s seconds of wall time.
+ * The fastest schedule is written to *out (its time in *best_ms, may be
+ * NULL) and cached on the graph: with budget_s <= 0 a cached winner is
+ * returned without timing. Timing-based, so repeated tuning may differ.
+ */
+gg_status gg_autotune(gg_graph *g, int32_t algo, double budget_s, const int32_t *probe_srcs, int32_t nprobe,
+                      gg_stream_t stream, gg_schedule *out, double *best_ms);
+
 /* Device bytes of workspace a query of `algo` with k sources needs on g. */
 gg_status gg_workspace_bytes(const gg_graph *g, int32_t algo, int32_t k, size_t *out);
 

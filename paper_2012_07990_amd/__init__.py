@@ -123,6 +123,7 @@ _sig("gg_bc", [_P, _i32, _SP, _P, _P, _P, _STP])
 _sig("gg_bfs_multi", [_P, _P, _i32, _SP, _P, _P, _STP])
 _sig("gg_bc_multi", [_P, _P, _i32, _SP, _P, _P, _P, _STP])
 _sig("gg_workspace_bytes", [_P, _i32, _i32, ctypes.POINTER(ctypes.c_size_t)])
+_sig("gg_autotune", [_P, _i32, ctypes.c_double, _P, _i32, _P, _SP, ctypes.POINTER(ctypes.c_double)])
 
 
 class GGError(RuntimeError):
@@ -366,6 +367,15 @@ class Graph:
                                                  ctypes.c_void_p(seg.ctypes.data), _stream(None)),
                "gg_graph_edgeblocking_export")
         return src[:self.m], dst[:self.m], seg
+
+    def autotune(self, algo: int, budget_s: float = 10.0, probes: Sequence[int] = (0,)):
+        """Run the library's autotuner; returns (schedule, best_ms)."""
+        a = np.ascontiguousarray(np.asarray(probes, dtype=np.int32))
+        s = Schedule()
+        ms = ctypes.c_double()
+        _check(_lib.gg_autotune(self.handle, int(algo), float(budget_s), ctypes.c_void_p(a.ctypes.data),
+                                int(a.size), _stream(None), ctypes.byref(s), ctypes.byref(ms)), "gg_autotune")
+        return s, ms.value
 
     def validate(self, algo: int, sched: Schedule) -> None:
         _check(_lib.gg_schedule_validate(self.handle, algo, ctypes.byref(sched)), "gg_schedule_validate")

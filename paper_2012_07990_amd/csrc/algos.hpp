@@ -23,6 +23,9 @@ void msbfs_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &s, int32
 void msbc_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &s, uint64_t *sigma, float *delta,
               hipStream_t stream, gg_stats *st);
 
+gg_schedule autotune(Graph &G, int algo, double budget_s, const int32_t *probes, int nprobe, hipStream_t st,
+                     double *best_ms);
+
 // EdgeBlocking preprocessing; returns milliseconds
 double edgeblock_prepare(Ctx &c, Graph &G, int32_t seg_vertices);
 

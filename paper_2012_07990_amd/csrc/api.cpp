@@ -325,6 +325,19 @@ gg_status gg_bc_multi(gg_graph *g, const int32_t *srcs_host, int32_t k, const gg
     });
 }
 
+gg_status gg_autotune(gg_graph *g, int32_t algo, double budget_s, const int32_t *probe_srcs, int32_t nprobe,
+                      gg_stream_t stream, gg_schedule *out, double *best_ms) {
+    return guarded([&] {
+        check_graph(g);
+        require(out != nullptr, GG_ERR_INVALID_ARG, "out is NULL");
+        require(algo >= GG_ALGO_BFS && algo <= GG_ALGO_BC, GG_ERR_INVALID_ARG, "unknown algorithm");
+        require(nprobe >= 0 && (nprobe == 0 || probe_srcs), GG_ERR_INVALID_ARG, "bad probe sources");
+        if (algo == GG_ALGO_CC || algo == GG_ALGO_PR || algo == GG_ALGO_BC)
+            require(g->g.symmetric, GG_ERR_INVALID_ARG, "this algorithm needs a symmetric graph (GG_SYMMETRIC)");
+        *out = autotune(g->g, algo, budget_s, probe_srcs, nprobe, S(stream), best_ms);
+    });
+}
+
 gg_status gg_workspace_bytes(const gg_graph *g, int32_t algo, int32_t k, size_t *out) {
     return guarded([&] {
         check_graph(g);

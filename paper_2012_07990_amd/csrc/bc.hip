@@ -14,6 +14,7 @@
 // with FP64 arithmetic in an order fixed by v's degree alone (deterministic,
 // so batched and single-source runs give identical bits); delta(src) = 0.
 #include "algos.hpp"
+#include "bc.hpp"
 #include "driver.hpp"
 
 namespace gg {
@@ -173,12 +174,11 @@ __global__ __launch_bounds__(kBlock) void k_bc_pull(DevGraph g, int32_t *depth, 
 // the whole workgroup (lane-strided partials, butterfly per wave, waves in
 // order). The multi-source pass uses the same rule, so results are bitwise
 // identical between single and batched runs.
-constexpr int kBcWaveDeg = 64, kBcBlockDeg = 4096;
 
 __device__ __forceinline__ double bc_term(const DevGraph &g, int e, int dv1, double sv, const int32_t *depth,
-                                          const unsigned long long *sigma, const double *delta) {
+                                          const unsigned long long *sigma, const double *delta, double acc) {
     const int w = g.col[e];
-    return depth[w] == dv1 ? (sv / (double)sigma[w]) * (1.0 + delta[w]) : 0.0;
+    return depth[w] == dv1 ? bc_step(acc, sv, (double)sigma[w], delta[w]) : acc;
 }
 
 __global__ __launch_bounds__(kBlock) void k_bc_backward(DevGraph g, const int32_t *level_ids, int count,
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_bc_backward(DevGraph g, const int32_
                 const int dv1 = depth[v] + 1;
                 const double sv = (double)sigma[v];
                 double acc = 0.0;
-                for (int e = g.row_ptr[v]; e < g.row_ptr[v + 1]; e++) acc += bc_term(g, e, dv1, sv, depth, sigma, delta);
+                for (int e = g.row_ptr[v]; e < g.row_ptr[v + 1]; e++) acc = bc_term(g, e, dv1, sv, depth, sigma, delta, acc);
                 delta[v] = acc;
             } else {
                 const int k = atomicAdd(&q_n[deg < kBcBlockDeg ? 0 : 1], 1);
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_bc_backward(DevGraph g, const int32_
             const double sv = (double)sigma[v];
             double acc = 0.0;
             for (int e = g.row_ptr[v] + lane; e < g.row_ptr[v + 1]; e += kWave)
-                acc += bc_term(g, e, dv1, sv, depth, sigma, delta);
+                acc = bc_term(g, e, dv1, sv, depth, sigma, delta, acc);
             acc = wave_sum(acc);
             if (lane == 0) delta[v] = acc;
         }
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(kBlock) void k_bc_backward(DevGraph g, const int32_
             const double sv = (double)sigma[v];
             double acc = 0.0;
             for (int e = g.row_ptr[v] + tid; e < g.row_ptr[v + 1]; e += kBlock)
-                acc += bc_term(g, e, dv1, sv, depth, sigma, delta);
+                acc = bc_term(g, e, dv1, sv, depth, sigma, delta, acc);
             acc = wave_sum(acc);
             __syncthreads();
             if (lane == 0) s_w[wib] = acc;

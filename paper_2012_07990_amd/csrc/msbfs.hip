@@ -1,0 +1,455 @@
+// Batched multi-source BFS and BC: up to 64 sources share one level-
+// synchronous traversal with bit-packed frontiers (bit j of a vertex's word
+// is source j), so each edge's column and frontier word are read once for
+// all sources.
+//
+// Per vertex: visited (sources that reached it), front (sources that reached
+// it at the current level), next. A level is a PULL sweep: every vertex
+// still missing some sources ORs its neighbours' front words, keeps the new
+// bits, records their level and (BC) adds each new source's path counts
+// sigma_j(u) over the parents u with bit j in front. Per-vertex state is
+// stored vertex-major (the K values of a vertex share a cache line) and
+// transposed into the k x n row-major outputs at the end.
+//
+// BC runs the backward pass level by level for all sources at once; every
+// (source, vertex) dependency is summed in exactly the order of the single-
+// source pass (same degree tiers, same lane striding, same butterflies, the
+// same non-contracted step), so batched results equal k single calls bit
+// for bit.
+#include "algos.hpp"
+#include "bc.hpp"
+#include "driver.hpp"
+
+namespace gg {
+
+using u64 = unsigned long long;
+
+__global__ __launch_bounds__(kBlock) void k_ms_init(int n, int K, const int32_t *srcs, u64 *visited, u64 *front,
+                                                    int32_t *depth_vm, u64 *sigma_vm, double *delta_vm) {
+    __shared__ int s_src[64];
+    if (threadIdx.x < 64) s_src[threadIdx.x] = threadIdx.x < K ? srcs[threadIdx.x] : -1;
+    __syncthreads();
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
+        u64 mask = 0;
+        for (int j = 0; j < K; j++)
+            if (s_src[j] == v) mask |= 1ull << j;
+        visited[v] = mask;
+        front[v] = mask;
+        for (int j = 0; j < K; j++) {
+            const bool on = (mask >> j) & 1ull;
+            depth_vm[(size_t)v * K + j] = on ? 0 : -1;
+            if (sigma_vm) {
+                sigma_vm[(size_t)v * K + j] = on ? 1ull : 0ull;
+                delta_vm[(size_t)v * K + j] = 0.0;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ u64 wave_or(u64 x) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) x |= __shfl_xor(x, off, kWave);
+    return x;
+}
+
+// record the level of the new sources of v
+__device__ __forceinline__ void ms_record(int32_t *depth_vm, int K, int v, u64 nb, int level) {
+    while (nb) {
+        const int j = __ffsll(nb) - 1;
+        depth_vm[(size_t)v * K + j] = level;
+        nb &= nb - 1;
+    }
+}
+
+// ---- multi-source BFS level (PULL with early exit once every missing source is found)
+__global__ __launch_bounds__(kBlock) void k_msbfs_pull(DevGraph g, int K, u64 all, u64 *visited, const u64 *front,
+                                                       u64 *next, int32_t *depth_vm, int level, int32_t *any) {
+    __shared__ int q_v[kBlock];
+    __shared__ int q_n;
+    const int tid = threadIdx.x, lane = lane_id(), wib = tid / kWave;
+    bool found_any = false;
+    for (int base = blockIdx.x * kBlock; base < g.n; base += gridDim.x * kBlock) {
+        if (tid == 0) q_n = 0;
+        __syncthreads();
+        const int v = base + tid;
+        if (v < g.n) {
+            const u64 need = all & ~visited[v];
+            const int beg = g.row_ptr[v], end = g.row_ptr[v + 1];
+            if (need == 0 || end == beg) {
+                next[v] = 0;
+            } else if (end - beg < kWave) {
+                u64 acc = 0;
+                for (int e = beg; e < end; e++) {
+                    acc |= front[g.col[e]];
+                    if ((acc & need) == need) break;
+                }
+                const u64 nb = acc & need;
+                next[v] = nb;
+                if (nb) {
+                    visited[v] |= nb;
+                    ms_record(depth_vm, K, v, nb, level);
+                    found_any = true;
+                }
+            } else {
+                q_v[atomicAdd(&q_n, 1)] = v;
+            }
+        }
+        __syncthreads();
+        for (int k = wib; k < q_n; k += kBlock / kWave) {
+            const int vv = q_v[k];
+            const u64 need = all & ~visited[vv];
+            u64 acc = 0;
+            for (int e = g.row_ptr[vv] + lane; e < g.row_ptr[vv + 1]; e += kWave) acc |= front[g.col[e]];
+            acc = wave_or(acc);
+            const u64 nb = acc & need;
+            if (lane == 0) {
+                next[vv] = nb;
+                if (nb) {
+                    visited[vv] |= nb;
+                    ms_record(depth_vm, K, vv, nb, level);
+                    found_any = true;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (__any(found_any) && lane_id() == 0) *any = 1;
+}
+
+// ---- multi-source BC forward level: new sources and their path counts -----------------
+constexpr int kBcGroup = 16;  // sources per BC pass (sigma / delta of a vertex: 128 B)
+
+__global__ __launch_bounds__(kBlock) void k_msbc_pull(DevGraph g, int K, u64 all, u64 *visited, const u64 *front,
+                                                      u64 *next, int32_t *depth_vm, u64 *sigma_vm, int level,
+                                                      int32_t *flags /* [0] any, [1] overflow */) {
+    __shared__ int q_v[kBlock];
+    __shared__ int q_n;
+    const int tid = threadIdx.x, lane = lane_id(), wib = tid / kWave;
+    bool found_any = false, wrap = false;
+    for (int base = blockIdx.x * kBlock; base < g.n; base += gridDim.x * kBlock) {
+        if (tid == 0) q_n = 0;
+        __syncthreads();
+        const int v = base + tid;
+        if (v < g.n) {
+            const u64 need = all & ~visited[v];
+            const int beg = g.row_ptr[v], end = g.row_ptr[v + 1];
+            if (need == 0 || end == beg) {
+                next[v] = 0;
+            } else if (end - beg < kWave) {
+                u64 acc = 0, sacc[kBcGroup];
+#pragma unroll
+                for (int j = 0; j < kBcGroup; j++) sacc[j] = 0;
+                for (int e = beg; e < end; e++) {
+                    const int u = g.col[e];
+                    const u64 f = front[u] & need;
+                    if (!f) continue;
+                    acc |= f;
+#pragma unroll
+                    for (int j = 0; j < kBcGroup; j++)
+                        if ((f >> j) & 1ull) {
+                            const u64 su = sigma_vm[(size_t)u * K + j];
+                            wrap |= sacc[j] + su < sacc[j];
+                            sacc[j] += su;
+                        }
+                }
+                next[v] = acc;
+                if (acc) {
+                    visited[v] |= acc;
+                    ms_record(depth_vm, K, v, acc, level);
+#pragma unroll
+                    for (int j = 0; j < kBcGroup; j++)
+                        if ((acc >> j) & 1ull) sigma_vm[(size_t)v * K + j] = sacc[j];
+                    found_any = true;
+                }
+            } else {
+                q_v[atomicAdd(&q_n, 1)] = v;
+            }
+        }
+        __syncthreads();
+        for (int k = wib; k < q_n; k += kBlock / kWave) {
+            const int vv = q_v[k];
+            const u64 need = all & ~visited[vv];
+            u64 acc = 0, sacc[kBcGroup];
+#pragma unroll
+            for (int j = 0; j < kBcGroup; j++) sacc[j] = 0;
+            for (int e = g.row_ptr[vv] + lane; e < g.row_ptr[vv + 1]; e += kWave) {
+                const int u = g.col[e];
+                const u64 f = front[u] & need;
+                if (!f) continue;
+                acc |= f;
+#pragma unroll
+                for (int j = 0; j < kBcGroup; j++)
+                    if ((f >> j) & 1ull) {
+                        const u64 su = sigma_vm[(size_t)u * K + j];
+                        wrap |= sacc[j] + su < sacc[j];
+                        sacc[j] += su;
+                    }
+            }
+            acc = wave_or(acc);
+#pragma unroll
+            for (int j = 0; j < kBcGroup; j++) {
+#pragma unroll
+                for (int off = kWave / 2; off > 0; off >>= 1) {
+                    const u64 y = __shfl_xor(sacc[j], off, kWave);
+                    wrap |= sacc[j] + y < sacc[j];
+                    sacc[j] += y;
+                }
+            }
+            if (lane == 0) {
+                next[vv] = acc;
+                if (acc) {
+                    visited[vv] |= acc;
+                    ms_record(depth_vm, K, vv, acc, level);
+#pragma unroll
+                    for (int j = 0; j < kBcGroup; j++)
+                        if ((acc >> j) & 1ull) sigma_vm[(size_t)vv * K + j] = sacc[j];
+                    found_any = true;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (__any(found_any) && lane_id() == 0) flags[0] = 1;
+    if (__any(wrap) && lane_id() == 0) flags[1] = 1;
+}
+
+// ---- multi-source BC backward level (same summation order as the single pass) -----------
+__global__ __launch_bounds__(kBlock) void k_msbc_backward(DevGraph g, int K, const int32_t *srcs, const int32_t *depth_vm,
+                                                          const u64 *sigma_vm, double *delta_vm, int level) {
+    __shared__ int q_v[2][kBlock];
+    __shared__ int q_n[2];
+    __shared__ double s_w[kBcGroup][kBlock / kWave];
+    __shared__ int s_src[kBcGroup];
+    const int tid = threadIdx.x, lane = lane_id(), wib = tid / kWave;
+    if (tid < kBcGroup) s_src[tid] = tid < K ? srcs[tid] : -1;
+    for (int base = blockIdx.x * kBlock; base < g.n; base += gridDim.x * kBlock) {
+        if (tid < 2) q_n[tid] = 0;
+        __syncthreads();
+        const int v = base + tid;
+        if (v < g.n) {
+            unsigned mask = 0;  // sources for which v sits at `level` (and is not the source)
+            for (int j = 0; j < K; j++)
+                if (depth_vm[(size_t)v * K + j] == level && s_src[j] != v) mask |= 1u << j;
+            if (mask) {
+                const int beg = g.row_ptr[v], end = g.row_ptr[v + 1];
+                const int deg = end - beg;
+                if (deg < kBcWaveDeg) {
+                    double acc[kBcGroup], sv[kBcGroup];
+#pragma unroll
+                    for (int j = 0; j < kBcGroup; j++) {
+                        acc[j] = 0.0;
+                        sv[j] = ((mask >> j) & 1u) ? (double)sigma_vm[(size_t)v * K + j] : 0.0;
+                    }
+                    for (int e = beg; e < end; e++) {
+                        const int w = g.col[e];
+#pragma unroll
+                        for (int j = 0; j < kBcGroup; j++)
+                            if (((mask >> j) & 1u) && depth_vm[(size_t)w * K + j] == level + 1)
+                                acc[j] = bc_step(acc[j], sv[j], (double)sigma_vm[(size_t)w * K + j],
+                                                 delta_vm[(size_t)w * K + j]);
+                    }
+#pragma unroll
+                    for (int j = 0; j < kBcGroup; j++)
+                        if ((mask >> j) & 1u) delta_vm[(size_t)v * K + j] = acc[j];
+                } else {
+                    const int t = deg < kBcBlockDeg ? 0 : 1;
+                    q_v[t][atomicAdd(&q_n[t], 1)] = v;
+                }
+            }
+        }
+        __syncthreads();
+        // one wavefront per vertex
+        for (int k = wib; k < q_n[0]; k += kBlock / kWave) {
+            const int vv = q_v[0][k];
+            unsigned mask = 0;
+            for (int j = 0; j < K; j++)
+                if (depth_vm[(size_t)vv * K + j] == level && s_src[j] != vv) mask |= 1u << j;
+            double acc[kBcGroup], sv[kBcGroup];
+#pragma unroll
+            for (int j = 0; j < kBcGroup; j++) {
+                acc[j] = 0.0;
+                sv[j] = ((mask >> j) & 1u) ? (double)sigma_vm[(size_t)vv * K + j] : 0.0;
+            }
+            for (int e = g.row_ptr[vv] + lane; e < g.row_ptr[vv + 1]; e += kWave) {
+                const int w = g.col[e];
+#pragma unroll
+                for (int j = 0; j < kBcGroup; j++)
+                    if (((mask >> j) & 1u) && depth_vm[(size_t)w * K + j] == level + 1)
+                        acc[j] = bc_step(acc[j], sv[j], (double)sigma_vm[(size_t)w * K + j],
+                                         delta_vm[(size_t)w * K + j]);
+            }
+#pragma unroll
+            for (int j = 0; j < kBcGroup; j++) {
+                const double r = wave_sum(acc[j]);
+                if (lane == 0 && ((mask >> j) & 1u)) delta_vm[(size_t)vv * K + j] = r;
+            }
+        }
+        // the whole workgroup per vertex
+        for (int k = 0; k < q_n[1]; k++) {
+            const int vv = q_v[1][k];
+            unsigned mask = 0;
+            for (int j = 0; j < K; j++)
+                if (depth_vm[(size_t)vv * K + j] == level && s_src[j] != vv) mask |= 1u << j;
+            double acc[kBcGroup], sv[kBcGroup];
+#pragma unroll
+            for (int j = 0; j < kBcGroup; j++) {
+                acc[j] = 0.0;
+                sv[j] = ((mask >> j) & 1u) ? (double)sigma_vm[(size_t)vv * K + j] : 0.0;
+            }
+            for (int e = g.row_ptr[vv] + tid; e < g.row_ptr[vv + 1]; e += kBlock) {
+                const int w = g.col[e];
+#pragma unroll
+                for (int j = 0; j < kBcGroup; j++)
+                    if (((mask >> j) & 1u) && depth_vm[(size_t)w * K + j] == level + 1)
+                        acc[j] = bc_step(acc[j], sv[j], (double)sigma_vm[(size_t)w * K + j],
+                                         delta_vm[(size_t)w * K + j]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < kBcGroup; j++) {
+                const double r = wave_sum(acc[j]);
+                if (lane == 0) s_w[j][wib] = r;
+            }
+            __syncthreads();
+            if (tid < kBcGroup && ((mask >> tid) & 1u)) {
+                double t = 0.0;
+                for (int w = 0; w < kBlock / kWave; w++) t += s_w[tid][w];
+                delta_vm[(size_t)vv * K + tid] = t;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---- vertex-major (n x K) -> row-major (rows j0.. of a k x n output), tiled through LDS
+template <class TI, class TO>
+__global__ __launch_bounds__(kBlock) void k_ms_transpose(const TI *in, int n, int K, TO *out, int j0) {
+    __shared__ TI tile[64][65];
+    for (int v0 = blockIdx.x * 64; v0 < n; v0 += gridDim.x * 64) {
+        for (int i = threadIdx.x; i < 64 * K; i += kBlock) {
+            const int dv = i / K, j = i % K;
+            if (v0 + dv < n) tile[j][dv] = in[(size_t)(v0 + dv) * K + j];
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < 64 * K; i += kBlock) {
+            const int j = i / 64, dv = i % 64;
+            if (v0 + dv < n) out[(size_t)(j0 + j) * n + v0 + dv] = (TO)tile[j][dv];
+        }
+        __syncthreads();
+    }
+}
+
+struct MsBuffers {
+    u64 *visited, *front, *next;
+    int32_t *depth_vm;
+};
+
+static MsBuffers ms_buffers(Workspace &ws, int n, int K) {
+    ws.aux_u64[0].ensure(n);
+    ws.aux_u64[1].ensure(n);
+    ws.aux_u64[2].ensure(n);
+    ws.aux_i32[3].ensure((size_t)n * (K > 0 ? K : 1));
+    return MsBuffers{ws.aux_u64[0].p, ws.aux_u64[1].p, ws.aux_u64[2].p, ws.aux_i32[3].p};
+}
+
+void msbfs_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &, int32_t *depth, hipStream_t stream,
+               gg_stats *st) {
+    Ctx c;
+    c.s = stream;
+    c.num_cus = G.num_cus;
+    StatsScope scope(st, c);
+    if (k == 0) { scope.finish(); return; }
+    Lease ws(G);
+    const DevGraph g = G.view();
+    const int n = g.n;
+    MsBuffers b = ms_buffers(*ws, n, k);
+    ws->counters.ensure(64);
+    ws->h_i32.ensure(16);
+    DevBuf<int32_t> dsrc;
+    dsrc.ensure(64);
+    GG_HIP(hipMemcpyAsync(dsrc.p, srcs, sizeof(int32_t) * k, hipMemcpyHostToDevice, c.s));
+    hipLaunchKernelGGL(k_ms_init, dim3(blocks_for(n, kBlock, 8192)), dim3(kBlock), 0, c.s, n, k, dsrc.p, b.visited,
+                       b.front, b.depth_vm, (u64 *)nullptr, (double *)nullptr);
+    GG_CHECK_LAUNCH();
+    c.launches++;
+    const u64 all = k == 64 ? ~0ull : ((1ull << k) - 1);
+    for (int level = 1;; level++) {
+        fill_i32(c, ws->counters.p, 1, 0);
+        hipLaunchKernelGGL(k_msbfs_pull, dim3(blocks_for(n, kBlock, 16384)), dim3(kBlock), 0, c.s, g, k, all, b.visited,
+                           b.front, b.next, b.depth_vm, level, ws->counters.p);
+        GG_CHECK_LAUNCH();
+        c.launches++;
+        std::swap(b.front, b.next);
+        if (st) { st->iterations++; st->pull_iterations++; }
+        if (read_i32(c, ws->counters.p, ws->h_i32.p) == 0) break;
+    }
+    hipLaunchKernelGGL((k_ms_transpose<int32_t, int32_t>), dim3(blocks_for(n, 64, 16384)), dim3(kBlock), 0, c.s,
+                       b.depth_vm, n, k, depth, 0);
+    GG_CHECK_LAUNCH();
+    c.launches++;
+    GG_HIP(hipStreamSynchronize(c.s));
+    scope.finish();
+}
+
+void msbc_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &, uint64_t *sigma_out, float *delta_out,
+              hipStream_t stream, gg_stats *st) {
+    Ctx c;
+    c.s = stream;
+    c.num_cus = G.num_cus;
+    StatsScope scope(st, c);
+    if (k == 0) { scope.finish(); return; }
+    Lease ws(G);
+    const DevGraph g = G.view();
+    const int n = g.n;
+    ws->counters.ensure(64);
+    ws->h_i32.ensure(16);
+    DevBuf<int32_t> dsrc;
+    dsrc.ensure(64);
+    GG_HIP(hipMemcpyAsync(dsrc.p, srcs, sizeof(int32_t) * k, hipMemcpyHostToDevice, c.s));
+    for (int j0 = 0; j0 < k; j0 += kBcGroup) {
+        const int K = std::min(kBcGroup, k - j0);
+        MsBuffers b = ms_buffers(*ws, n, K);
+        ws->aux_u64[0].ensure(n);
+        DevBuf<u64> &sig = ws->ms_sigma;
+        sig.ensure((size_t)n * K);
+        DevBuf<double> &del = ws->aux_f64[1];
+        del.ensure((size_t)n * K);
+        hipLaunchKernelGGL(k_ms_init, dim3(blocks_for(n, kBlock, 8192)), dim3(kBlock), 0, c.s, n, K, dsrc.p + j0,
+                           b.visited, b.front, b.depth_vm, sig.p, del.p);
+        GG_CHECK_LAUNCH();
+        c.launches++;
+        const u64 all = (1ull << K) - 1;
+        int levels = 1;  // levels present: 0 .. levels-1
+        for (int level = 1;; level++) {
+            fill_i32(c, ws->counters.p, 2, 0);
+            hipLaunchKernelGGL(k_msbc_pull, dim3(blocks_for(n, kBlock, 16384)), dim3(kBlock), 0, c.s, g, K, all,
+                               b.visited, b.front, b.next, b.depth_vm, sig.p, level, ws->counters.p);
+            GG_CHECK_LAUNCH();
+            c.launches++;
+            std::swap(b.front, b.next);
+            if (st) { st->iterations++; st->pull_iterations++; }
+            GG_HIP(hipMemcpyAsync(ws->h_i32.p, ws->counters.p, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
+            GG_HIP(hipStreamSynchronize(c.s));
+            require(ws->h_i32.p[1] == 0, GG_ERR_OVERFLOW, "a shortest-path count exceeds 2^64-1");
+            if (ws->h_i32.p[0] == 0) break;
+            levels = level + 1;
+        }
+        for (int level = levels - 2; level >= 0; level--) {
+            hipLaunchKernelGGL(k_msbc_backward, dim3(blocks_for(n, kBlock, 16384)), dim3(kBlock), 0, c.s, g, K,
+                               dsrc.p + j0, b.depth_vm, sig.p, del.p, level);
+            GG_CHECK_LAUNCH();
+            c.launches++;
+        }
+        hipLaunchKernelGGL((k_ms_transpose<u64, u64>), dim3(blocks_for(n, 64, 16384)), dim3(kBlock), 0, c.s, sig.p, n,
+                           K, reinterpret_cast<u64 *>(sigma_out), j0);
+        GG_CHECK_LAUNCH();
+        hipLaunchKernelGGL((k_ms_transpose<double, float>), dim3(blocks_for(n, 64, 16384)), dim3(kBlock), 0, c.s,
+                           del.p, n, K, delta_out, j0);
+        GG_CHECK_LAUNCH();
+        c.launches += 2;
+    }
+    GG_HIP(hipStreamSynchronize(c.s));
+    scope.finish();
+}
+
+}  // namespace gg

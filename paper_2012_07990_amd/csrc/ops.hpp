@@ -126,6 +126,7 @@ struct Workspace {
     DevBuf<double> pr_acc, pr_head, pr_tail;
     DevBuf<double> pr_partial, pr_dangling;
     DevBuf<unsigned> pr_done;
+    DevBuf<unsigned long long> ms_sigma;  // multi-source BC path counts (vertex-major)
     DevBuf<unsigned> barrier;             // grid barrier state for fused kernels
     HostPinned<int32_t> h_i32;            // pinned readback slots
     HostPinned<long long> h_i64;
@@ -162,6 +163,7 @@ struct Graph {
     int32_t max_degree = 0;
     std::map<int32_t, std::unique_ptr<EdgeBlocked>> eb;  // per blocking size
     std::map<int32_t, std::unique_ptr<PullBlocked>> pull_eb;  // STRICT pull partitions per segment width
+    std::map<int, std::pair<gg_schedule, double>> tuned;       // autotuner winners (schedule, ms) per algorithm
     std::mutex mu;
     std::vector<std::unique_ptr<Workspace>> pool;
     int device = 0;

@@ -1,0 +1,189 @@
+// Autotuner (Auto-tuning subsection of the Compiler Implementation section):
+// the valid schedules of an algorithm -- load balancing x direction /
+// hybrid threshold x frontier representation and creation x deduplication x
+// kernel fusion x delta x EdgeBlocking width -- are timed on the graph and
+// narrowed by successive halving (every round keeps the faster half and
+// doubles the number of timed runs per survivor) within a wall-clock budget.
+// The winner is cached on the graph per algorithm.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "algos.hpp"
+
+namespace gg {
+
+static gg_simple_schedule base_simple() { return default_schedule().s1; }
+
+static std::vector<gg_schedule> candidates(const Graph &G, int algo) {
+    std::vector<gg_schedule> out;
+    auto push = [&](const gg_schedule &s) {
+        try {
+            validate_schedule(G, algo, s);
+            out.push_back(s);
+        } catch (const Error &) {
+        }
+    };
+    const int lbs[] = {GG_LB_VERTEX_BASED, GG_LB_WM, GG_LB_CM, GG_LB_STRICT, GG_LB_TWC, GG_LB_ETWC, GG_LB_EDGE_ONLY};
+    const float thetas[] = {0.001f, 0.01f, 0.05f, 0.2f};
+    gg_schedule s = default_schedule();
+    switch (algo) {
+    case GG_ALGO_BFS:
+    case GG_ALGO_BC:
+        for (int lb : lbs) {
+            s = default_schedule();
+            s.s1.load_balance = lb;
+            push(s);  // push only
+            for (float th : thetas)
+                for (int rep : {GG_REP_BITMAP, GG_REP_BOOLMAP}) {
+                    gg_schedule h = s;
+                    h.hybrid = 1;
+                    h.threshold = th;
+                    h.s2 = base_simple();
+                    h.s2.direction = GG_PULL;
+                    h.s2.pull_rep = rep;
+                    h.s2.dedup_enable = 0;
+                    h.s2.frontier_creation = algo == GG_ALGO_BFS ? GG_CREATE_UNFUSED_BITMAP : GG_CREATE_FUSED;
+                    push(h);
+                }
+            if (algo == GG_ALGO_BFS) {
+                gg_schedule f = s;
+                f.s1.kernel_fusion = 1;
+                push(f);
+                gg_schedule fh = f;
+                fh.hybrid = 1;
+                fh.threshold = 0.01f;
+                fh.s2 = f.s1;
+                fh.s2.kernel_fusion = 0;
+                fh.s2.direction = GG_PULL;
+                fh.s2.pull_rep = GG_REP_BITMAP;
+                push(fh);
+            }
+        }
+        break;
+    case GG_ALGO_SSSP:
+        for (int lb : lbs)
+            for (int delta : {1, 8, 64, 512, 4096})
+                for (int fused : {0, 1}) {
+                    s = default_schedule();
+                    s.s1.load_balance = lb;
+                    s.s1.delta = delta;
+                    s.s1.kernel_fusion = fused;
+                    push(s);
+                }
+        break;
+    case GG_ALGO_CC:
+        for (int lb : lbs)
+            for (int fused : {0, 1}) {
+                s = default_schedule();
+                s.s1.load_balance = lb;
+                s.s1.kernel_fusion = fused;
+                push(s);
+            }
+        break;
+    case GG_ALGO_PR:
+        for (int lb : {GG_LB_VERTEX_BASED, GG_LB_WM, GG_LB_ETWC, GG_LB_STRICT}) {
+            s = default_schedule();
+            s.s1.direction = GG_PULL;
+            s.s1.load_balance = lb;
+            push(s);
+        }
+        s = default_schedule();
+        s.s1.load_balance = GG_LB_EDGE_ONLY;
+        push(s);
+        for (int lg = 17; lg <= 22; lg++) {
+            if ((1 << lg) >= G.n) break;
+            s = default_schedule();
+            s.s1.direction = GG_PULL;
+            s.s1.load_balance = GG_LB_STRICT;
+            s.s1.edge_blocking = 1;
+            s.s1.blocking_size = 1 << lg;
+            push(s);
+            s.s1.direction = GG_PUSH;
+            s.s1.load_balance = GG_LB_EDGE_ONLY;
+            push(s);
+        }
+        break;
+    default:
+        throw Error(GG_ERR_INVALID_ARG, "unknown algorithm");
+    }
+    return out;
+}
+
+// One timed run (seconds); the drivers synchronise before returning.
+static double time_one(Graph &G, int algo, const gg_schedule &s, int src, void *out1, void *out2, hipStream_t st) {
+    const auto t0 = std::chrono::steady_clock::now();
+    switch (algo) {
+    case GG_ALGO_BFS: bfs_run(G, src, s, (int32_t *)out1, st, nullptr); break;
+    case GG_ALGO_SSSP: sssp_run(G, src, s, (int32_t *)out1, st, nullptr); break;
+    case GG_ALGO_CC: cc_run(G, s, (int32_t *)out1, st, nullptr); break;
+    case GG_ALGO_PR: pr_run(G, s, 0.85f, 20, 0, (float *)out1, st, nullptr); break;
+    case GG_ALGO_BC: bc_run(G, src, s, (uint64_t *)out1, (float *)out2, st, nullptr); break;
+    }
+    GG_HIP(hipStreamSynchronize(st));
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+gg_schedule autotune(Graph &G, int algo, double budget_s, const int32_t *probes, int nprobe, hipStream_t st,
+                     double *best_ms) {
+    {
+        std::lock_guard<std::mutex> lk(G.mu);
+        auto it = G.tuned.find(algo);
+        if (it != G.tuned.end() && budget_s <= 0) {
+            if (best_ms) *best_ms = it->second.second;
+            return it->second.first;
+        }
+    }
+    if (algo == GG_ALGO_SSSP) require(G.has_weights, GG_ERR_INVALID_ARG, "SSSP needs edge weights");
+    std::vector<int> srcs;
+    for (int i = 0; i < nprobe; i++) {
+        require(probes[i] >= 0 && probes[i] < G.n, GG_ERR_INVALID_ARG, "probe source out of range");
+        srcs.push_back(probes[i]);
+    }
+    if (srcs.empty()) srcs.push_back(0);
+    const auto t0 = std::chrono::steady_clock::now();
+    auto elapsed = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
+    DevBuf<int64_t> o1, o2;
+    o1.ensure((size_t)G.n);
+    o2.ensure((size_t)G.n);
+    struct Cand {
+        gg_schedule s;
+        double t;
+    };
+    std::vector<Cand> cands;
+    for (auto &s : candidates(G, algo)) cands.push_back({s, 1e30});
+    require(!cands.empty(), GG_ERR_UNSUPPORTED_SCHEDULE, "no valid schedule to tune");
+    int runs = 1, probe_i = 0;
+    while (cands.size() > 1) {
+        for (auto &c : cands) {
+            double best = 1e30;
+            for (int r = 0; r < runs; r++) {
+                const int src = srcs[(probe_i + r) % srcs.size()];
+                try {
+                    best = std::min(best, time_one(G, algo, c.s, src, o1.p, o2.p, st));
+                } catch (const Error &e) {
+                    if (e.code == GG_ERR_DEVICE) throw;
+                    best = 1e30;  // e.g. a queue overflow without dedup: not a usable schedule
+                    break;
+                }
+            }
+            c.t = best;
+            if (elapsed() > budget_s && &c != &cands.front()) break;
+        }
+        std::stable_sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.t < b.t; });
+        if (elapsed() > budget_s) break;
+        cands.resize((cands.size() + 1) / 2);
+        runs *= 2;
+        probe_i += 1;
+    }
+    const Cand &w = cands.front();
+    if (best_ms) *best_ms = w.t * 1e3;
+    std::lock_guard<std::mutex> lk(G.mu);
+    G.tuned[algo] = {w.s, w.t * 1e3};
+    return w.s;
+}
+
+}  // namespace gg
