@@ -245,6 +245,64 @@ gg_status gg_autotune(gg_graph *g, int32_t algo, double budget_s, const int32_t 
 /* Device bytes of workspace a query of `algo` with k sources needs on g. */
 gg_status gg_workspace_bytes(const gg_graph *g, int32_t algo, int32_t k, size_t *out);
 
+/* ---- serving ------------------------------------------------------------------------- */
+/*
+ * A request loop over device-resident graphs. Queries are admitted by device-
+ * memory footprint (a query that could never fit the budget is refused with
+ * GG_ERR_ADMISSION at submission; others wait until memory frees up) and are
+ * batched continuously: whenever a worker stream is free it takes the oldest
+ * pending query together with every pending query of the same graph and
+ * algorithm (BFS up to 64 per bit-packed launch, BC up to 16; SSSP, CC and
+ * PageRank one per launch). Worker streams run concurrently. A query's result
+ * stays on the device, charged to the budget, until it is polled. Batched
+ * results are bit-identical to single-source calls, so a query's result does
+ * not depend on what it was batched with. Persistent (fused) schedules are not
+ * admitted in a server.
+ */
+typedef struct gg_server gg_server;
+
+typedef struct {
+    int64_t ticket;
+    int32_t status;      /* the query's gg_status */
+    int32_t graph_id, algo, src;
+    int32_t batch_size;  /* queries that shared its launch */
+    double queue_ms;     /* arrival -> start of its batch */
+    double latency_ms;   /* arrival -> result complete on the device */
+} gg_result;
+
+typedef struct {
+    int64_t submitted, completed, collected, rejected, batches;
+    int32_t max_batch;
+    size_t bytes_in_use, bytes_peak;
+    double busy_ms;      /* summed wall time of executed batches */
+} gg_serve_stats;
+
+#define GG_OUT_DEVICE 0u  /* `out` is device memory */
+#define GG_OUT_HOST 1u    /* `out` is host memory */
+#define GG_OUT_DISCARD 2u /* drop the result */
+
+/* hbm_budget: device bytes the server may hold for workspaces and results;
+   nstreams: concurrent worker streams (1..16). */
+gg_status gg_server_create(size_t hbm_budget, int32_t nstreams, gg_server **out);
+/* Register a symmetric graph (caller keeps ownership; it must outlive the
+   server). All graphs are added before the first query. */
+gg_status gg_server_add_graph(gg_server *srv, gg_graph *g, int32_t *gid);
+/* Override the schedule used for (graph, algorithm); default: the graph's
+   tuned schedule when it is not fused, else the power-law preset. */
+gg_status gg_server_set_schedule(gg_server *srv, int32_t gid, int32_t algo, const gg_schedule *s);
+gg_status gg_server_submit(gg_server *srv, int32_t gid, int32_t algo, int32_t src, int64_t *ticket);
+/* Non-blocking: GG_ERR_NOT_READY while running. When done, copies the result
+   (BFS/SSSP/CC: int32[n]; PR: float[n]; BC: uint64[n] sigma then float[n]
+   delta) to `out` per `flags` (NULL or GG_OUT_DISCARD drops it), releases it
+   and returns the query's status. GG_ERR_NOT_FOUND for unknown tickets. */
+gg_status gg_server_poll(gg_server *srv, int64_t ticket, void *out, uint32_t flags, gg_result *res);
+/* As poll, blocking up to timeout_s seconds (< 0: no limit). */
+gg_status gg_server_wait(gg_server *srv, int64_t ticket, double timeout_s, void *out, uint32_t flags,
+                         gg_result *res);
+gg_status gg_server_stats(gg_server *srv, gg_serve_stats *out);
+/* Runs the pending queries to completion, frees uncollected results. */
+gg_status gg_server_destroy(gg_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

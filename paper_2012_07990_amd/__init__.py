@@ -126,6 +126,36 @@ _sig("gg_workspace_bytes", [_P, _i32, _i32, ctypes.POINTER(ctypes.c_size_t)])
 _sig("gg_autotune", [_P, _i32, ctypes.c_double, _P, _i32, _P, _SP, ctypes.POINTER(ctypes.c_double)])
 
 
+class Result(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_int64), ("status", ctypes.c_int32), ("graph_id", ctypes.c_int32),
+                ("algo", ctypes.c_int32), ("src", ctypes.c_int32), ("batch_size", ctypes.c_int32),
+                ("queue_ms", ctypes.c_double), ("latency_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("collected", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("batches", ctypes.c_int64), ("max_batch", ctypes.c_int32),
+                ("bytes_in_use", ctypes.c_size_t), ("bytes_peak", ctypes.c_size_t), ("busy_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+OUT_DEVICE, OUT_HOST, OUT_DISCARD = 0, 1, 2
+_RP = ctypes.POINTER(Result)
+_sig("gg_server_create", [ctypes.c_size_t, _i32, ctypes.POINTER(_P)])
+_sig("gg_server_add_graph", [_P, _P, ctypes.POINTER(_i32)])
+_sig("gg_server_set_schedule", [_P, _i32, _i32, _SP])
+_sig("gg_server_submit", [_P, _i32, _i32, _i32, ctypes.POINTER(_i64)])
+_sig("gg_server_poll", [_P, _i64, _P, _u32, _RP])
+_sig("gg_server_wait", [_P, _i64, ctypes.c_double, _P, _u32, _RP])
+_sig("gg_server_stats", [_P, ctypes.POINTER(ServeStats)])
+_sig("gg_server_destroy", [_P])
+
+
 class GGError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -384,6 +414,73 @@ class Graph:
         out = ctypes.c_size_t()
         _check(_lib.gg_workspace_bytes(self.handle, algo, k, ctypes.byref(out)), "gg_workspace_bytes")
         return out.value
+
+
+class Server:
+    """Serving loop (gg_server_*): admission by device-memory footprint and
+    continuous batching of queries over registered graphs."""
+
+    def __init__(self, budget_bytes: int, nstreams: int = 4):
+        h = ctypes.c_void_p()
+        _check(_lib.gg_server_create(int(budget_bytes), int(nstreams), ctypes.byref(h)), "gg_server_create")
+        self.handle = h
+        self.graphs = []
+
+    def add_graph(self, G: Graph) -> int:
+        gid = ctypes.c_int32()
+        _check(_lib.gg_server_add_graph(self.handle, G.handle, ctypes.byref(gid)), "gg_server_add_graph")
+        self.graphs.append(G)
+        return gid.value
+
+    def set_schedule(self, gid: int, algo: int, sched: Schedule):
+        _check(_lib.gg_server_set_schedule(self.handle, gid, algo, ctypes.byref(sched)), "gg_server_set_schedule")
+
+    def submit(self, gid: int, algo: int, src: int) -> int:
+        t = ctypes.c_int64()
+        _check(_lib.gg_server_submit(self.handle, gid, algo, int(src), ctypes.byref(t)), "gg_server_submit")
+        return t.value
+
+    def _out(self, out):
+        if out is None:
+            return None, OUT_DISCARD
+        if isinstance(out, np.ndarray):
+            return ctypes.c_void_p(out.ctypes.data), OUT_HOST
+        return _dptr(out), OUT_DEVICE
+
+    def poll(self, ticket: int, out=None):
+        """None while running; else the result record (copying the result into `out`)."""
+        p, fl = self._out(out)
+        r = Result()
+        st = _lib.gg_server_poll(self.handle, int(ticket), p, fl, ctypes.byref(r))
+        if st == ERR_NOT_READY:
+            return None
+        _check(st, "gg_server_poll")
+        return r.as_dict()
+
+    def wait(self, ticket: int, timeout: float = -1.0, out=None):
+        p, fl = self._out(out)
+        r = Result()
+        st = _lib.gg_server_wait(self.handle, int(ticket), float(timeout), p, fl, ctypes.byref(r))
+        if st == ERR_NOT_READY:
+            return None
+        _check(st, "gg_server_wait")
+        return r.as_dict()
+
+    def stats(self):
+        s = ServeStats()
+        _check(_lib.gg_server_stats(self.handle, ctypes.byref(s)), "gg_server_stats")
+        return s.as_dict()
+
+    def close(self):
+        if self.handle:
+            _lib.gg_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def header_functions() -> list:

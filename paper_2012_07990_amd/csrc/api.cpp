@@ -9,11 +9,14 @@
 #include <vector>
 
 #include "algos.hpp"
+#include "handles.hpp"
 #include "ops.hpp"
 
 using namespace gg;
 
-static thread_local std::string g_last_error;
+namespace gg {
+thread_local std::string g_last_error;
+}
 
 template <class Fn>
 static gg_status guarded(Fn &&fn) {
@@ -35,10 +38,6 @@ static gg_status guarded(Fn &&fn) {
         return GG_ERR_DEVICE;
     }
 }
-
-struct gg_graph {
-    Graph g;
-};
 
 namespace gg {
 

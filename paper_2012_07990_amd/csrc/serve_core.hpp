@@ -1,0 +1,111 @@
+// Serving core: admission by device-memory footprint and continuous batching
+// of queued traversal queries, independent of the device (an Executor runs
+// the batches), so the scheduling policy is testable on a CPU.
+//
+// Policy. A query whose single-query footprint exceeds the budget is refused
+// at submission. Worker threads (one per device stream) repeatedly take the
+// oldest pending query and add every other pending query for the same graph
+// and algorithm, up to the executor's batch limit and the memory still free
+// (budget minus running batches minus results not yet collected). A batch
+// that does not fit waits until memory frees up; queries that arrive while
+// others run are picked up by the next free worker, so batches of different
+// sizes run concurrently on different streams. A result stays charged to the
+// budget until the client collects it.
+#pragma once
+
+#include <chrono>
+#include <condition_variable>
+#include <cstddef>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <thread>
+#include <vector>
+
+namespace gg {
+namespace serve {
+
+using Clock = std::chrono::steady_clock;
+
+// thrown by submit() when a single query can never fit the memory budget
+struct AdmissionError : std::runtime_error {
+    explicit AdmissionError(const std::string &m) : std::runtime_error(m) {}
+};
+
+struct Req {
+    int64_t ticket = 0;
+    int gid = 0, algo = 0, src = 0;
+    Clock::time_point t_arrive, t_start, t_done;
+    int status = 0;          // 0 ok, else a gg_status code
+    int batch_size = 0;
+    size_t result_bytes = 0;
+    void *result = nullptr;  // executor-owned result storage
+    bool done = false;
+};
+
+struct Batch {
+    int gid = 0, algo = 0;
+    std::vector<Req *> reqs;
+    size_t work_bytes = 0;  // transient footprint while the batch runs
+};
+
+class Executor {
+public:
+    virtual ~Executor() = default;
+    virtual int max_batch(int algo) const = 0;
+    // device bytes a batch of k queries needs while it runs (results excluded)
+    virtual size_t work_bytes(int gid, int algo, int k) const = 0;
+    // device bytes one query's result occupies until collected
+    virtual size_t result_bytes(int gid, int algo) const = 0;
+    // run the batch on the worker's stream; fill each Req's status / result
+    virtual void run(int worker, Batch &b) = 0;
+    // free one collected result
+    virtual void release(Req &r) = 0;
+};
+
+struct Stats {
+    int64_t submitted = 0, completed = 0, rejected = 0, batches = 0, collected = 0;
+    int32_t max_batch_seen = 0;
+    size_t bytes_in_use = 0, bytes_peak = 0;
+    double busy_ms = 0;
+};
+
+class Core {
+public:
+    Core(Executor *ex, size_t budget, int workers);
+    ~Core();
+    // returns the ticket; throws AdmissionError if a single query can never fit
+    int64_t submit(int gid, int algo, int src);
+    // true when the query is done; copies its record (result stays charged until collect)
+    bool peek(int64_t ticket, Req &out);
+    // block until done or timeout (seconds, < 0 = forever); true when done
+    bool wait(int64_t ticket, double timeout_s, Req &out);
+    // release a done query's result (after the caller copied it); false if unknown
+    bool collect(int64_t ticket);
+    bool known(int64_t ticket);
+    Stats stats();
+    void shutdown();
+
+private:
+    void worker(int id);
+    bool form_batch(Batch &b);  // called with mu held
+
+    Executor *ex_;
+    size_t budget_;
+    std::mutex mu_;
+    std::condition_variable cv_work_, cv_done_;
+    std::deque<Req *> pending_;
+    std::map<int64_t, std::unique_ptr<Req>> reqs_;
+    std::vector<std::thread> threads_;
+    int64_t next_ticket_ = 1;
+    size_t in_use_ = 0;
+    bool stop_ = false;
+    Stats st_;
+};
+
+}  // namespace serve
+}  // namespace gg

@@ -1,0 +1,158 @@
+// CPU test of the serving core's policy with a fake executor (no device):
+// admission refusal, continuous batching per (graph, algorithm), the memory
+// budget (including uncollected results) and result delivery.
+#include <atomic>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <thread>
+
+#include "../../paper_2012_07990_amd/csrc/serve_core.hpp"
+
+using namespace gg::serve;
+
+#define CHECK(c)                                                               \
+    do {                                                                       \
+        if (!(c)) {                                                            \
+            std::fprintf(stderr, "FAILED %s:%d: %s\n", __FILE__, __LINE__, #c); \
+            std::exit(1);                                                      \
+        }                                                                      \
+    } while (0)
+
+struct Fake : Executor {
+    size_t work_per = 100, result_per = 10;
+    int sleep_ms = 2;
+    std::atomic<int> running{0}, max_running{0};
+    std::atomic<int> mixed{0};
+    int max_batch(int algo) const override { return algo == 0 ? 64 : algo == 4 ? 16 : 1; }
+    size_t work_bytes(int, int, int k) const override { return work_per * (size_t)k; }
+    size_t result_bytes(int, int) const override { return result_per; }
+    void run(int, Batch &b) override {
+        int r = ++running;
+        int m = max_running.load();
+        while (r > m && !max_running.compare_exchange_weak(m, r)) {}
+        for (Req *q : b.reqs)
+            if (q->gid != b.gid || q->algo != b.algo) mixed++;
+        std::this_thread::sleep_for(std::chrono::milliseconds(sleep_ms));
+        for (Req *q : b.reqs) {
+            int *v = (int *)std::malloc(sizeof(int));
+            *v = q->src * 3 + q->algo;
+            q->result = v;
+            q->status = q->src < 0 ? 5 : 0;
+        }
+        --running;
+    }
+    void release(Req &r) override {
+        std::free(r.result);
+        r.result = nullptr;
+    }
+};
+
+static void test_admission() {
+    Fake f;
+    Core c(&f, 50, 1);
+    bool threw = false;
+    try {
+        c.submit(0, 0, 1);
+    } catch (const AdmissionError &) {
+        threw = true;
+    }
+    CHECK(threw);
+    CHECK(c.stats().rejected == 1);
+    std::puts("ok admission");
+}
+
+static void test_batching_and_results() {
+    Fake f;
+    f.sleep_ms = 20;
+    Core c(&f, 1 << 30, 1);
+    std::vector<int64_t> t;
+    for (int i = 0; i < 200; i++) t.push_back(c.submit(i % 2, 0, i));  // two graphs, BFS
+    for (int i = 0; i < 200; i++) {
+        Req r;
+        CHECK(c.wait(t[i], 10.0, r));
+        CHECK(r.status == 0 && *(int *)r.result == i * 3);
+        CHECK(r.batch_size >= 1 && r.batch_size <= 64);
+        CHECK(c.collect(t[i]));
+    }
+    const Stats s = c.stats();
+    CHECK(s.completed == 200 && s.collected == 200);
+    CHECK(s.max_batch_seen > 1);       // queued queries were batched
+    CHECK(s.batches < 200);
+    CHECK(f.mixed.load() == 0);        // a batch never mixes graphs or algorithms
+    CHECK(s.bytes_in_use == 0);
+    std::puts("ok batching");
+}
+
+static void test_budget_limits_batch_and_concurrency() {
+    Fake f;
+    f.sleep_ms = 5;
+    Core c(&f, 400, 4);  // at most 3 queries (3 * 110) in flight
+    std::vector<int64_t> t;
+    for (int i = 0; i < 60; i++) t.push_back(c.submit(0, 0, i));
+    for (auto x : t) {
+        Req r;
+        CHECK(c.wait(x, 10.0, r));
+        CHECK(r.batch_size <= 3);
+        CHECK(c.collect(x));
+    }
+    CHECK(c.stats().bytes_peak <= 400);
+    std::puts("ok budget");
+}
+
+static void test_uncollected_results_hold_memory() {
+    Fake f;
+    f.sleep_ms = 1;
+    f.work_per = 10;
+    f.result_per = 100;
+    Core c(&f, 230, 2);  // two queries fit (2 * 110); their results (2 * 100) stay charged
+    int64_t a = c.submit(0, 1, 1), b = c.submit(0, 1, 2);  // SSSP: no batching
+    Req r;
+    CHECK(c.wait(a, 5.0, r));
+    CHECK(c.wait(b, 5.0, r));
+    int64_t d = c.submit(0, 1, 3);
+    std::this_thread::sleep_for(std::chrono::milliseconds(50));
+    CHECK(!c.peek(d, r));            // blocked: both results still held
+    CHECK(c.collect(a));
+    CHECK(c.wait(d, 5.0, r));        // runs once memory was released
+    CHECK(*(int *)r.result == 3 * 3 + 1);
+    std::puts("ok hold");
+}
+
+static void test_failed_query_frees_memory() {
+    Fake f;
+    Core c(&f, 1000, 1);
+    int64_t a = c.submit(0, 1, -1);
+    Req r;
+    CHECK(c.wait(a, 5.0, r));
+    CHECK(r.status == 5);
+    CHECK(c.collect(a));
+    CHECK(c.stats().bytes_in_use == 0);
+    std::puts("ok failure");
+}
+
+static void test_concurrent_workers_overlap() {
+    Fake f;
+    f.sleep_ms = 30;
+    Core c(&f, 1 << 30, 4);
+    std::vector<int64_t> t;
+    for (int g = 0; g < 4; g++) t.push_back(c.submit(g, 1, g));  // four independent SSSP queries
+    for (auto x : t) {
+        Req r;
+        CHECK(c.wait(x, 5.0, r));
+        c.collect(x);
+    }
+    CHECK(f.max_running.load() >= 2);
+    std::puts("ok overlap");
+}
+
+int main() {
+    test_admission();
+    test_batching_and_results();
+    test_budget_limits_batch_and_concurrency();
+    test_uncollected_results_hold_memory();
+    test_failed_query_frees_memory();
+    test_concurrent_workers_overlap();
+    std::puts("ALL OK");
+    return 0;
+}
