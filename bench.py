@@ -26,6 +26,22 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, GB/s
 
 
+def measured_traffic(kernel_src: str, summary: str):
+    """HBM bytes per launch from a committed rocprofv3 summary, when that
+    summary was taken on the current kernel source (else None)."""
+    import hashlib
+    import re
+    try:
+        h = hashlib.sha256(open(os.path.join(ROOT, kernel_src), "rb").read()).hexdigest()[:16]
+        txt = open(os.path.join(ROOT, "profiles", summary)).read()
+    except OSError:
+        return None
+    if h not in txt:
+        return None
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    return float(m.group(1)) if m else None
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -36,6 +52,15 @@ def parse():
     p.add_argument("--only", default="", help="comma list of algorithms to run (bfs,sssp,cc,pr,bc)")
     p.add_argument("--sweep", action="store_true", help="time every schedule family per algorithm")
     p.add_argument("--verbose", action="store_true")
+    p.add_argument("--no-batched", action="store_true", help="skip the batched multi-source section")
+    p.add_argument("--no-serving", action="store_true", help="skip the serving section")
+    p.add_argument("--serve-rates", default="500,5000", help="Poisson arrival rates (queries/s)")
+    p.add_argument("--serve-seconds", type=float, default=1.0)
+    p.add_argument("--serve-budget-s", type=float, default=150.0, help="wall-clock cap of the serving section")
+    p.add_argument("--grid", type=int, default=0,
+                   help="also time BFS/SSSP on a WxW road-like grid (fused vs unfused, delta sweep)")
+    p.add_argument("--serve-full", action="store_true",
+                   help="serve the full four-graph mix (adds R-MAT 23) at 100..5000 q/s")
     return p.parse_args()
 
 
@@ -210,16 +235,23 @@ def main():
         torch.cuda.synchronize()
         per_launch_ms = st.kernel_ms / max(st.kernel_launches, 1)
         n, m = g.n, g.m
-        alg_bytes = 8.0 * m + 16.0 * n  # per round: col + contrib gather per edge; row_ptr, rank, contrib per vertex
+        alg_bytes = 8.0 * m + 8.0 * n  # per launch: col + gathered contribution per edge, fp64 accumulator per vertex
         achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9
+        traffic = measured_traffic("paper_2012_07990_amd/csrc/pr.hip", "k_pr_strict_chunks_rmat22.md")
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "kernel": st.kernel_name.decode() if isinstance(st.kernel_name, bytes) else str(st.kernel_name),
                 "per_launch_ms": round(per_launch_ms, 5), "bytes_per_launch": alg_bytes}
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(g, src, reached_edges)
+    G.close()
+    del G
+
+    grid = grid_section(gg, graphgen, torch, args.grid) if args.grid else None
+    batched = None if args.no_batched else batched_section(gg, graphgen, torch)
+    serving = None if args.no_serving else serving_section(gg, graphgen, torch, args)
 
     rec = {
         "metric": "GTEPS per algorithm (BFS/SSSP/CC/PR/BC); batched queries/s + p99 latency",
@@ -232,9 +264,204 @@ def main():
         "per_algo": per,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "grid": grid,
+        "batched": batched,
+        "serving": serving,
     }
     print(json.dumps(rec), flush=True)
+
+
+def grid_section(gg, graphgen, torch, W):
+    """High-diameter road-like grid: SSSP over delta in {1, 8, 64, 512} and BFS,
+    each fused (one persistent launch) and unfused (one launch per round)."""
+    g = graphgen.grid(W)
+    G = gg.Graph.from_graphgen(g)
+    out = {"workload": "grid %dx%d, 10%% non-tree edges dropped, weights 1..999, source 0" % (W, W),
+           "n": g.n, "m": g.m, "runs": []}
+    for algo in ["bfs", "sssp"]:
+        for delta in ([1, 8, 64, 512] if algo == "sssp" else [0]):
+            for fused in (True, False):
+                sch = gg.make_schedule(lb="cm", delta=max(delta, 1), fusion=fused)
+                run = (lambda: G.sssp(0, sch, stats=st)) if algo == "sssp" else (lambda: G.bfs(0, sch, stats=st))
+                st = gg.Stats()
+                t1 = time.perf_counter()
+                run()
+                torch.cuda.synchronize()
+                ms = 1e3 * (time.perf_counter() - t1)
+                if ms < 20000:  # a second timed run when the first was not too long
+                    st = gg.Stats()
+                    t1 = time.perf_counter()
+                    run()
+                    torch.cuda.synchronize()
+                    ms = 1e3 * (time.perf_counter() - t1)
+                rec = {"algo": algo, "delta": delta if algo == "sssp" else None, "fused": fused, "ms": round(ms, 3),
+                       "rounds": st.iterations, "buckets": st.buckets, "launches": st.launches,
+                       "us_per_round": round(1e3 * ms / max(st.iterations, 1), 2)}
+                log("grid: %s" % rec)
+                out["runs"].append(rec)
     G.close()
+    return out
+
+
+def batched_section(gg, graphgen, torch):
+    """64 BFS + 16 BC sources on R-MAT 20 in one batched call each, against the
+    same sources as single-source calls (bit-identity checked on the way)."""
+    import numpy as np
+    g = graphgen.rmat(20)
+    G = gg.Graph.from_graphgen(g)
+    deg = g.degrees()
+    bfs_src = graphgen.sample_sources(g, 64, 7)
+    bc_src = bfs_src[:16]
+    sb = gg.schedule_preset(gg.ALGO_BFS, gg.PRESET_POWERLAW)
+    sb.threshold = 0.01
+    sc = gg.schedule_preset(gg.ALGO_BC, gg.PRESET_POWERLAW)
+    sc.threshold = 0.01
+
+    def timed(f, reps=3):
+        f()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t1 = time.perf_counter()
+            f()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t1)
+        return sorted(ts)[len(ts) // 2]
+
+    d_multi = G.bfs_multi(bfs_src)
+    s_multi, dl_multi = G.bc_multi(bc_src)
+    ok = True
+    for i in range(0, 64, 9):
+        ok &= bool(torch.equal(d_multi[i], G.bfs(int(bfs_src[i]), sb)))
+    for i in range(0, 16, 5):
+        s1, d1 = G.bc(int(bc_src[i]), sc)
+        ok &= bool(torch.equal(s_multi[i], s1)) and bool(torch.equal(dl_multi[i].view(torch.int32),
+                                                                        d1.view(torch.int32)))
+    t_multi = timed(lambda: (G.bfs_multi(bfs_src), G.bc_multi(bc_src)))
+    t_single = timed(lambda: ([G.bfs(int(x), sb) for x in bfs_src], [G.bc(int(x), sc) for x in bc_src]), reps=1)
+    reach = d_multi.cpu().numpy() >= 0
+    edges = float(sum(deg[reach[i]].sum() for i in range(64)))
+    reach_bc = s_multi.cpu().numpy() != 0
+    edges += float(sum(deg[reach_bc[i]].sum() for i in range(16)))
+    G.close()
+    log("batched: multi %.2f ms, single %.2f ms, speedup %.2fx, identical=%s" %
+        (t_multi * 1e3, t_single * 1e3, t_single / t_multi, ok))
+    return {"workload": "rmat20: 64 BFS + 16 BC sources (uniform over non-isolated vertices, seed 7)",
+            "ms_batched": round(t_multi * 1e3, 3), "ms_single_calls": round(t_single * 1e3, 3),
+            "speedup": round(t_single / t_multi, 2), "gteps_batched": round(edges / t_multi / 1e9, 2),
+            "queries_per_s": round(80 / t_multi, 1), "bit_identical": ok}
+
+
+def serving_section(gg, graphgen, torch, args):
+    """Poisson streams of mixed BFS/SSSP/BC queries over resident graphs, served
+    with continuous batching, against one query per launch in arrival order."""
+    import numpy as np
+    gspecs = [("rmat18", lambda: graphgen.rmat(18, weights=True)), ("rmat20", lambda: graphgen.rmat(20, weights=True)),
+              ("grid2048", lambda: graphgen.grid(2048))]
+    if args.serve_full:
+        gspecs.append(("rmat23", lambda: graphgen.rmat(23, weights=True)))
+    hg = [f() for _, f in gspecs]
+    Gs = [gg.Graph.from_graphgen(g) for g in hg]
+    cand = [np.nonzero(g.degrees() > 0)[0] for g in hg]
+    rates = [float(x) for x in args.serve_rates.split(",")] if not args.serve_full else [100, 500, 1000, 2000, 5000]
+    rng = np.random.default_rng(11)
+    is_rmat = [name.startswith("rmat") for name, _ in gspecs]
+
+    def make_stream(rate, seconds):
+        n = max(1, int(rate * seconds))
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n))
+        qs = []
+        for t in arrivals:
+            gi = int(rng.integers(0, len(Gs)))
+            u = rng.random()
+            algo = gg.ALGO_BFS if u < 0.5 else (gg.ALGO_SSSP if u < 0.85 else gg.ALGO_BC)
+            if algo == gg.ALGO_BC and not is_rmat[gi]:
+                algo = gg.ALGO_BFS
+            src = int(cand[gi][int(rng.integers(0, cand[gi].size))])
+            qs.append((float(t), gi, algo, src))
+        return qs
+
+    def pct(xs, p):
+        return float(np.percentile(np.asarray(xs), p)) if xs else None
+
+    out = {"graphs": [name for name, _ in gspecs], "mix": "BFS 50% / SSSP 35% / BC 15% (BC on R-MAT only)",
+           "rates": []}
+    budget = 16 << 30
+    # per-graph schedules: power-law preset on R-MAT; on the high-diameter grid
+    # delta-stepping runs as one persistent loop (alone on the device)
+    grid_sssp = gg.make_schedule(lb="cm", delta=512, fusion=True)
+    sec0 = time.perf_counter()
+    for rate in rates:
+        if time.perf_counter() - sec0 > args.serve_budget_s:
+            log("serving: wall-clock cap reached, rate %g skipped" % rate)
+            break
+        qs = make_stream(rate, args.serve_seconds)
+        srv = gg.Server(budget_bytes=budget, nstreams=4)
+        gids = [srv.add_graph(G) for G in Gs]
+        for gi, (name, _) in enumerate(gspecs):
+            if name.startswith("grid"):
+                srv.set_schedule(gids[gi], gg.ALGO_SSSP, grid_sssp)
+        log("serving: rate %g, %d queries" % (rate, len(qs)))
+        t0 = time.perf_counter()
+        tickets = []
+        for (ta, gi, algo, src) in qs:
+            now = time.perf_counter() - t0
+            if ta > now:
+                time.sleep(ta - now)
+            tickets.append(srv.submit(gids[gi], algo, src))
+        lat = []
+        done = 0
+        for i, t in enumerate(tickets):
+            r = srv.wait(t, 60.0)
+            if r is None:
+                log("serving: query %d still running after 60 s, stopping the wait" % i)
+                break
+            lat.append(r["latency_ms"])
+            done += 1
+            if done % 500 == 0:
+                log("serving: %d/%d done" % (done, len(tickets)))
+        t_end = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        served_qps = done / t_end
+        # baseline: one query per launch, in arrival order, on one stream
+        # (same schedules; bounded to 30 s of wall time)
+        sched = {gg.ALGO_BFS: gg.schedule_preset(gg.ALGO_BFS, gg.PRESET_POWERLAW),
+                 gg.ALGO_BC: gg.schedule_preset(gg.ALGO_BC, gg.PRESET_POWERLAW),
+                 gg.ALGO_SSSP: gg.schedule_preset(gg.ALGO_SSSP, gg.PRESET_POWERLAW)}
+        sched[gg.ALGO_SSSP].s1.delta = 64
+        blat = []
+        nb = 0
+        t1 = time.perf_counter()
+        for (ta, gi, algo, src) in qs:
+            now = time.perf_counter() - t1
+            if now > 30.0:
+                break
+            if ta > now:
+                time.sleep(ta - now)
+            G = Gs[gi]
+            if algo == gg.ALGO_BFS:
+                G.bfs(src, sched[algo])
+            elif algo == gg.ALGO_SSSP:
+                G.sssp(src, grid_sssp if gspecs[gi][0].startswith("grid") else sched[algo])
+            else:
+                G.bc(src, sched[algo])
+            torch.cuda.synchronize()
+            blat.append((time.perf_counter() - t1 - ta) * 1e3)
+            nb += 1
+        tb = time.perf_counter() - t1
+        base_qps = nb / tb
+        rec = {"rate_qps": rate, "queries": len(qs), "completed": done, "served_qps": round(served_qps, 1),
+               "p50_ms": round(pct(lat, 50), 3), "p99_ms": round(pct(lat, 99), 3),
+               "max_batch": st["max_batch"], "batches": st["batches"],
+               "baseline_qps": round(base_qps, 1), "baseline_p50_ms": round(pct(blat, 50), 3),
+               "baseline_p99_ms": round(pct(blat, 99), 3), "baseline_queries": nb,
+               "throughput_ratio": round(served_qps / base_qps, 2)}
+        log("serving rate %g: %s" % (rate, rec))
+        out["rates"].append(rec)
+    for G in Gs:
+        G.close()
+    return out
 
 
 def cpu_baseline(g, src, reached_edges):

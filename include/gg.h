@@ -256,8 +256,8 @@ gg_status gg_workspace_bytes(const gg_graph *g, int32_t algo, int32_t k, size_t 
  * PageRank one per launch). Worker streams run concurrently. A query's result
  * stays on the device, charged to the budget, until it is polled. Batched
  * results are bit-identical to single-source calls, so a query's result does
- * not depend on what it was batched with. Persistent (fused) schedules are not
- * admitted in a server.
+ * not depend on what it was batched with. A query whose schedule is a
+ * persistent (fused) loop runs alone on the device (other batches wait).
  */
 typedef struct gg_server gg_server;
 

@@ -3,10 +3,13 @@
 // queries of one graph are batched up to 64 into one bit-packed traversal,
 // BC queries up to 16; SSSP, CC and PageRank run one query per launch. Every
 // worker owns a default-priority stream, so batches of different graphs and
-// algorithms overlap on the device.
+// algorithms overlap on the device. A query whose schedule is a persistent
+// (fused) loop takes the device exclusively: its co-resident grid assumes
+// no other kernel occupies the compute units.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <shared_mutex>
 
 #include "algos.hpp"
 #include "handles.hpp"
@@ -21,6 +24,8 @@ struct GpuExecutor : serve::Executor {
     std::vector<hipStream_t> streams;
     std::mutex mu;
     std::map<std::pair<int, int>, gg_schedule> sched;
+    // a persistent (fused) loop assumes the whole device: it runs alone
+    std::shared_mutex device;
 
     explicit GpuExecutor(int workers) {
         for (int i = 0; i < workers; i++) {
@@ -67,6 +72,11 @@ struct GpuExecutor : serve::Executor {
         const size_t n = (size_t)G.n;
         const int k = (int)b.reqs.size();
         const gg_schedule s = schedule_for(b.gid, b.algo);
+        const bool fused = k == 1 && s.s1.kernel_fusion;
+        std::shared_lock<std::shared_mutex> shared(device, std::defer_lock);
+        std::unique_lock<std::shared_mutex> exclusive(device, std::defer_lock);
+        if (fused) exclusive.lock();
+        else shared.lock();
         try {
             for (serve::Req *r : b.reqs) GG_HIP(hipMallocAsync(&r->result, r->result_bytes, st));
             if (k == 1) {
@@ -200,8 +210,6 @@ gg_status gg_server_set_schedule(gg_server *srv, int32_t gid, int32_t algo, cons
     return sguard([&] {
         require(srv && s, GG_ERR_INVALID_ARG, "NULL argument");
         require(gid >= 0 && gid < srv->ex->ngraphs, GG_ERR_INVALID_ARG, "unknown graph id");
-        require(!s->s1.kernel_fusion, GG_ERR_UNSUPPORTED_SCHEDULE,
-                "served queries share the device: persistent (fused) loops are not admitted");
         validate_schedule(*srv->ex->graphs[gid], algo, *s);
         std::lock_guard<std::mutex> lk(srv->ex->mu);
         srv->ex->sched[{gid, algo}] = *s;

@@ -67,8 +67,29 @@ def test_serving_admission_and_errors():
         srv.poll(12345)
     assert e.value.status == gg.ERR_NOT_FOUND
     with pytest.raises(gg.GGError) as e:
-        srv.set_schedule(gid, gg.ALGO_BFS, gg.make_schedule(fusion=True))
+        srv.set_schedule(gid, gg.ALGO_BFS, gg.make_schedule(lb="twc", fusion=True))
     assert e.value.status == gg.ERR_UNSUPPORTED_SCHEDULE
+    srv.close()
+
+
+def test_serving_fused_schedule_runs_exclusively():
+    names = ["grid64", "rmat12"]
+    Gs = [dev_graph(n) for n in names]
+    srv = gg.Server(budget_bytes=1 << 30, nstreams=3)
+    gids = [srv.add_graph(G) for G in Gs]
+    srv.set_schedule(gids[0], gg.ALGO_SSSP, gg.make_schedule(lb="cm", delta=64, fusion=True))
+    qs = []
+    for i in range(60):
+        gi = i % 2
+        algo = gg.ALGO_SSSP if i % 3 else gg.ALGO_BFS
+        src = (i * 37) % Gs[gi].n
+        qs.append((gi, algo, src, srv.submit(gids[gi], algo, src)))
+    for gi, algo, src, t in qs:
+        out = np.empty(Gs[gi].n, dtype=np.int32)
+        r = srv.wait(t, 60.0, out=out)
+        assert r["status"] == gg.OK
+        exp = oracle_sssp(names[gi], src) if algo == gg.ALGO_SSSP else oracle_bfs(names[gi], src)
+        assert_int_equal(out, exp)
     srv.close()
 
 
