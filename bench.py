@@ -24,11 +24,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, GB/s
+PR_SEGMENT = 1 << 20   # PageRank pull EdgeBlocking: source segments of 2^20 vertices
 
 
-def measured_traffic(kernel_src: str, summary: str):
+def measured_traffic(kernel_src: str, summary: str, schedule_tag: str):
     """HBM bytes per launch from a committed rocprofv3 summary, when that
-    summary was taken on the current kernel source (else None)."""
+    summary was taken on the current kernel source under the same schedule
+    (else None)."""
     import hashlib
     import re
     try:
@@ -36,7 +38,7 @@ def measured_traffic(kernel_src: str, summary: str):
         txt = open(os.path.join(ROOT, "profiles", summary)).read()
     except OSError:
         return None
-    if h not in txt:
+    if h not in txt or ("schedule: %s" % schedule_tag) not in txt:
         return None
     m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     return float(m.group(1)) if m else None
@@ -59,6 +61,8 @@ def parse():
     p.add_argument("--serve-budget-s", type=float, default=150.0, help="wall-clock cap of the serving section")
     p.add_argument("--grid", type=int, default=0,
                    help="also time BFS/SSSP on a WxW road-like grid (fused vs unfused, delta sweep)")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run a plain 1 GiB device copy three times (scales rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     p.add_argument("--serve-full", action="store_true",
                    help="serve the full four-graph mix (adds R-MAT 23) at 100..5000 q/s")
     return p.parse_args()
@@ -74,7 +78,7 @@ def schedules(gg):
     bfs.threshold = 0.01
     sssp = gg.make_schedule(lb="etwc", delta=64)
     cc = gg.make_schedule(lb="etwc")
-    pr = gg.make_schedule(lb="strict", direction=gg.PULL)
+    pr = gg.make_schedule(lb="strict", direction=gg.PULL, edge_blocking=True, blocking_size=PR_SEGMENT)
     bc = gg.schedule_preset(gg.ALGO_BC, gg.PRESET_POWERLAW)
     bc.threshold = 0.01
     return {"bfs": bfs, "sssp": sssp, "cc": cc, "pr": pr, "bc": bc}
@@ -85,6 +89,13 @@ def sweep_schedules(gg):
     for lb in ["vp", "wm", "cm", "strict", "twc", "etwc"]:
         out["bfs"]["push-" + lb] = gg.make_schedule(lb=lb)
         out["cc"][lb] = gg.make_schedule(lb=lb)
+        out["cc"]["fused-" + lb] = gg.make_schedule(lb=lb, fusion=True)
+    for th in [0.005, 0.01, 0.02]:
+        for lb in ["strict", "twc", "cm"]:
+            s = gg.schedule_preset(gg.ALGO_BFS, gg.PRESET_POWERLAW)
+            s.s1.load_balance = gg.LB_NAMES[lb]
+            s.threshold = th
+            out["bfs"]["hybrid-%s-%g" % (lb, th)] = s
     out["cc"]["edge_only"] = gg.make_schedule(lb="edge_only")
     for th in [0.001, 0.01, 0.05, 0.2]:
         s = gg.schedule_preset(gg.ALGO_BFS, gg.PRESET_BFS_HYBRID)
@@ -96,10 +107,12 @@ def sweep_schedules(gg):
     out["bfs"]["fused-vp"] = gg.make_schedule(lb="vp", fusion=True)
     out["bfs"]["fused-hybrid"] = gg.make_schedule(lb="vp", fusion=True, threshold=0.01,
                                                   hybrid={"direction": gg.PULL, "pull_rep": gg.REP_BITMAP})
-    for d in [1, 8, 64, 512, 4096]:
-        for lb in ["vp", "etwc", "cm"]:
+    for d in [16, 64, 256, 1024]:
+        for lb in ["wm", "etwc", "cm", "strict", "twc"]:
             out["sssp"]["%s-d%d" % (lb, d)] = gg.make_schedule(lb=lb, delta=d)
         out["sssp"]["fused-etwc-d%d" % d] = gg.make_schedule(lb="etwc", delta=d, fusion=True)
+    out["sssp"]["strict-d64-nodedup"] = gg.make_schedule(lb="strict", delta=64, dedup=False)
+    out["sssp"]["strict-d64-bitmapdedup"] = gg.make_schedule(lb="strict", delta=64, dedup_type=gg.DEDUP_BITMAP)
     for lb in ["vp", "wm", "etwc", "strict"]:
         out["pr"]["pull-" + lb] = gg.make_schedule(lb=lb, direction=gg.PULL)
     out["pr"]["push-edge"] = gg.make_schedule(lb="edge_only")
@@ -108,8 +121,12 @@ def sweep_schedules(gg):
     for N in [1 << 17, 1 << 18, 1 << 19, 1 << 20, 1 << 21]:
         out["pr"]["pull-strict-eb-%d" % N] = gg.make_schedule(lb="strict", direction=gg.PULL, edge_blocking=True,
                                                               blocking_size=N)
-    for lb in ["vp", "etwc"]:
+    for lb in ["vp", "etwc", "strict", "twc"]:
         out["bc"]["push-" + lb] = gg.make_schedule(lb=lb)
+        s = gg.schedule_preset(gg.ALGO_BC, gg.PRESET_POWERLAW)
+        s.s1.load_balance = gg.LB_NAMES[lb]
+        s.threshold = 0.01
+        out["bc"]["hybrid-%s-0.01" % lb] = s
     for th in [0.001, 0.01, 0.05]:
         s = gg.schedule_preset(gg.ALGO_BC, gg.PRESET_POWERLAW)
         s.threshold = th
@@ -125,6 +142,16 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        torch.cuda.set_device(0)
+        a = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copied %d bytes x3" % (4 * a.numel()))
+        return
 
     import graphgen
     import paper_2012_07990_amd as gg
@@ -234,14 +261,28 @@ def main():
         run("pr", scheds["pr"], st)
         torch.cuda.synchronize()
         per_launch_ms = st.kernel_ms / max(st.kernel_launches, 1)
-        n, m = g.n, g.m
-        alg_bytes = 8.0 * m + 8.0 * n  # per launch: col + gathered contribution per edge, fp64 accumulator per vertex
+        # algorithmic bytes of one round: per edge its 4-byte column and the
+        # 4-byte contribution it gathers; per (row, source segment) pair with
+        # edges, one fp64 accumulator read and written. A launch covers one
+        # segment, so a round's bytes are spread over its launches.
+        m = g.m
+        seg = g.col // PR_SEGMENT
+        chg = np.empty(m, dtype=bool)
+        chg[0] = True
+        chg[1:] = seg[1:] != seg[:-1]
+        chg[g.row_ptr[:-1][deg > 0]] = True
+        pairs = int(chg.sum())
+        del seg, chg
+        launches_per_round = st.kernel_launches / 20.0
+        alg_bytes = (8.0 * m + 16.0 * pairs) / launches_per_round
         achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9
-        traffic = measured_traffic("paper_2012_07990_amd/csrc/pr.hip", "k_pr_strict_chunks_rmat22.md")
+        traffic = measured_traffic("paper_2012_07990_amd/csrc/pr.hip", "k_pr_strict_chunks_rmat22.md",
+                                   "PULL+STRICT+EB(%d)" % PR_SEGMENT)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "kernel": st.kernel_name.decode() if isinstance(st.kernel_name, bytes) else str(st.kernel_name),
-                "per_launch_ms": round(per_launch_ms, 5), "bytes_per_launch": alg_bytes}
+                "per_launch_ms": round(per_launch_ms, 5), "bytes_per_launch": round(alg_bytes),
+                "launches_per_round": launches_per_round, "row_segment_pairs": pairs}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -343,13 +384,36 @@ def batched_section(gg, graphgen, torch):
     edges = float(sum(deg[reach[i]].sum() for i in range(64)))
     reach_bc = s_multi.cpu().numpy() != 0
     edges += float(sum(deg[reach_bc[i]].sum() for i in range(16)))
-    G.close()
     log("batched: multi %.2f ms, single %.2f ms, speedup %.2fx, identical=%s" %
         (t_multi * 1e3, t_single * 1e3, t_single / t_multi, ok))
-    return {"workload": "rmat20: 64 BFS + 16 BC sources (uniform over non-isolated vertices, seed 7)",
-            "ms_batched": round(t_multi * 1e3, 3), "ms_single_calls": round(t_single * 1e3, 3),
-            "speedup": round(t_single / t_multi, 2), "gteps_batched": round(edges / t_multi / 1e9, 2),
-            "queries_per_s": round(80 / t_multi, 1), "bit_identical": ok}
+    out = {"workload": "rmat20: 64 BFS + 16 BC sources (uniform over non-isolated vertices, seed 7)",
+           "ms_batched": round(t_multi * 1e3, 3), "ms_single_calls": round(t_single * 1e3, 3),
+           "speedup": round(t_single / t_multi, 2), "gteps_batched": round(edges / t_multi / 1e9, 2),
+           "queries_per_s": round(80 / t_multi, 1), "bit_identical": ok}
+    # 64 SSSP sources: on R-MAT 20 (delta 64) and on the 2048^2 grid (delta 512),
+    # against single calls (on the grid 4 single calls stand for the 64)
+    out["sssp"] = []
+    for name, Gx, srcs, single_s, nsingle in [
+            ("rmat20", G, bfs_src, gg.make_schedule(lb="etwc", delta=64), 64),
+            ("grid2048", None, None, gg.make_schedule(lb="cm", delta=512, fusion=True), 4)]:
+        if Gx is None:
+            gh = graphgen.grid(2048)
+            Gx = gg.Graph.from_graphgen(gh)
+            srcs = graphgen.sample_sources(gh, 64, 7)
+        ms_s = gg.make_schedule(delta=single_s.s1.delta)
+        st = gg.Stats()
+        dm = Gx.sssp_multi(srcs, ms_s, stats=st)
+        ok_s = all(bool(torch.equal(dm[i], Gx.sssp(int(srcs[i]), single_s))) for i in range(0, 64, 21))
+        t_m = timed(lambda: Gx.sssp_multi(srcs, ms_s), reps=1 if name.startswith("grid") else 3)
+        t_1 = timed(lambda: [Gx.sssp(int(x), single_s) for x in srcs[:nsingle]], reps=1) * 64 / nsingle
+        rec = {"graph": name, "k": 64, "delta": int(single_s.s1.delta), "ms_batched": round(t_m * 1e3, 3),
+               "ms_single_calls": round(t_1 * 1e3, 3), "single_calls_timed": nsingle,
+               "speedup": round(t_1 / t_m, 2), "rounds": st.iterations, "buckets": st.buckets,
+               "queries_per_s": round(64 / t_m, 1), "bit_identical": ok_s}
+        log("batched sssp: %s" % rec)
+        out["sssp"].append(rec)
+        Gx.close()
+    return out
 
 
 def serving_section(gg, graphgen, torch, args):

@@ -224,6 +224,15 @@ gg_status gg_bc(gg_graph *g, int32_t src, const gg_schedule *s, uint64_t *sigma_
    row-major. Bit-identical to k gg_bfs calls. */
 gg_status gg_bfs_multi(gg_graph *g, const int32_t *srcs_host, int32_t k, const gg_schedule *s,
                        int32_t *depth_dev, gg_stream_t stream, gg_stats *stats);
+/* k <= 64 delta-stepping SSSP sources (host array) sharing one bucket loop
+   in one persistent launch (configDelta of the Scheduling Language section;
+   Kernel Fusion across Iterations): dist_dev is k x n row-major int32,
+   unreached = INT32_MAX. The schedule contributes s1.delta (>= 1) only; the
+   batch always runs fused. Requires weights and max degree < 2^25.
+   GG_ERR_OVERFLOW when any source's distance would exceed INT32_MAX-1.
+   Bit-identical to k gg_sssp calls. */
+gg_status gg_sssp_multi(gg_graph *g, const int32_t *srcs_host, int32_t k, const gg_schedule *s,
+                        int32_t *dist_dev, gg_stream_t stream, gg_stats *stats);
 /* k <= 64 BC sources; sigma_dev / delta_dev are k x n row-major.
    Bit-identical to k gg_bc calls. */
 gg_status gg_bc_multi(gg_graph *g, const int32_t *srcs_host, int32_t k, const gg_schedule *s,

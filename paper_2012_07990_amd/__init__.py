@@ -121,6 +121,7 @@ _sig("gg_cc", [_P, _SP, _P, _P, _STP])
 _sig("gg_pagerank", [_P, _SP, ctypes.c_float, _i32, _u32, _P, _P, _STP])
 _sig("gg_bc", [_P, _i32, _SP, _P, _P, _P, _STP])
 _sig("gg_bfs_multi", [_P, _P, _i32, _SP, _P, _P, _STP])
+_sig("gg_sssp_multi", [_P, _P, _i32, _SP, _P, _P, _STP])
 _sig("gg_bc_multi", [_P, _P, _i32, _SP, _P, _P, _P, _STP])
 _sig("gg_workspace_bytes", [_P, _i32, _i32, ctypes.POINTER(ctypes.c_size_t)])
 _sig("gg_autotune", [_P, _i32, ctypes.c_double, _P, _i32, _P, _SP, ctypes.POINTER(ctypes.c_double)])
@@ -267,6 +268,12 @@ def gg_bfs_multi(graph, srcs, sched, depth, stream=None, stats=None):
                              _dptr(depth), _stream(stream), _stats_ptr(stats)), "gg_bfs_multi")
 
 
+def gg_sssp_multi(graph, srcs, sched, dist, stream=None, stats=None):
+    a = np.ascontiguousarray(np.asarray(srcs, dtype=np.int32))
+    _check(_lib.gg_sssp_multi(graph.handle, ctypes.c_void_p(a.ctypes.data), int(a.size), _sched_ptr(sched),
+                              _dptr(dist), _stream(stream), _stats_ptr(stats)), "gg_sssp_multi")
+
+
 def gg_bc_multi(graph, srcs, sched, sigma, delta, stream=None, stats=None):
     a = np.ascontiguousarray(np.asarray(srcs, dtype=np.int32))
     _check(_lib.gg_bc_multi(graph.handle, ctypes.c_void_p(a.ctypes.data), int(a.size), _sched_ptr(sched),
@@ -372,6 +379,12 @@ class Graph:
         torch = _torch()
         out = self._empty((len(srcs), self.n), torch.int32)
         gg_bfs_multi(self, srcs, sched, out, stats=stats)
+        return out
+
+    def sssp_multi(self, srcs: Sequence[int], sched=None, stats=None):
+        torch = _torch()
+        out = self._empty((len(srcs), self.n), torch.int32)
+        gg_sssp_multi(self, srcs, sched, out, stats=stats)
         return out
 
     def bc_multi(self, srcs: Sequence[int], sched=None, stats=None):

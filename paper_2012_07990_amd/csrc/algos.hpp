@@ -20,6 +20,11 @@ void bc_run(Graph &G, int32_t src, const gg_schedule &s, uint64_t *sigma, float 
             gg_stats *st);
 void msbfs_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &s, int32_t *depth, hipStream_t stream,
                gg_stats *st);
+// overflow_mask: when non-null, receives the sources whose distances overflow
+// (instead of an exception)
+void mssssp_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &s, int32_t *dist, hipStream_t stream,
+                gg_stats *st, unsigned long long *overflow_mask);
+size_t mssssp_work_bytes(const Graph &G, int k);
 void msbc_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &s, uint64_t *sigma, float *delta,
               hipStream_t stream, gg_stats *st);
 

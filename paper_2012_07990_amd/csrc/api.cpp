@@ -310,6 +310,20 @@ gg_status gg_bfs_multi(gg_graph *g, const int32_t *srcs_host, int32_t k, const g
     });
 }
 
+gg_status gg_sssp_multi(gg_graph *g, const int32_t *srcs_host, int32_t k, const gg_schedule *s, int32_t *dist_dev,
+                        gg_stream_t stream, gg_stats *stats) {
+    return guarded([&] {
+        check_graph(g);
+        require(k >= 0 && k <= 64, GG_ERR_INVALID_ARG, "k must be in [0, 64]");
+        require(k == 0 || (srcs_host && dist_dev), GG_ERR_INVALID_ARG, "NULL sources or output");
+        for (int i = 0; i < k; i++)
+            require(srcs_host[i] >= 0 && srcs_host[i] < g->g.n, GG_ERR_INVALID_ARG, "source out of range");
+        require(g->g.has_weights, GG_ERR_INVALID_ARG, "SSSP needs edge weights");
+        const gg_schedule sc = s ? *s : default_schedule();
+        mssssp_run(g->g, srcs_host, k, sc, dist_dev, S(stream), stats, nullptr);
+    });
+}
+
 gg_status gg_bc_multi(gg_graph *g, const int32_t *srcs_host, int32_t k, const gg_schedule *s, uint64_t *sigma_dev,
                       float *delta_dev, gg_stream_t stream, gg_stats *stats) {
     return guarded([&] {

@@ -167,7 +167,7 @@ void bfs_fused(Ctx &c, Graph &G, Workspace &ws, int32_t src, const gg_schedule &
     GG_CHECK_LAUNCH();
     fill_i32(c, ws.counters.p, 1, 1);  // |F0| = 1
     c.launches++;
-    const int blocks = fused_grid(kern, 2, c.num_cus);
+    const int blocks = fused_grid_for(kern, G, c.num_cus);
     FusedBfsArgs a{g, depth, ws.q[0].p, ws.q[1].p, ws.counters.p, ws.boolmap[0].p, ws.bitmap[0].p,
                    s.threshold, prepare_barrier(c, ws, blocks), c.edge_counter};
     void *args[] = {&a};

@@ -117,7 +117,7 @@ void cc_run(Graph &G, const gg_schedule &sch, int32_t *label, hipStream_t stream
         case GG_LB_ETWC: kern = (const void *)k_cc_fused<GG_LB_ETWC>; break;
         default: throw Error(GG_ERR_UNSUPPORTED_SCHEDULE, "kernel fusion supports VERTEX_BASED, WM, CM and ETWC");
         }
-        const int blocks = fused_grid(kern, 2, c.num_cus);
+        const int blocks = fused_grid_for(kern, G, c.num_cus);
         FusedCcArgs a{g, label, ws->aux_i32[0].p, ws->counters.p, prepare_barrier(c, *ws, blocks), c.edge_counter};
         void *args[] = {&a};
         launch_cooperative(c, kern, blocks, args);

@@ -84,6 +84,7 @@ __device__ __forceinline__ bool grid_sync(GridBarrier &b) {
 // Co-resident grid for a persistent kernel: `per_cu` workgroups per compute
 // unit, capped by the occupancy the kernel actually achieves.
 int fused_grid(const void *kernel, int per_cu, int num_cus);
+int fused_grid_for(const void *kernel, const Graph &G, int num_cus);
 
 // Launch with the cooperative API (which refuses grids that cannot be
 // co-resident).

@@ -19,6 +19,7 @@
 #include "algos.hpp"
 #include "bc.hpp"
 #include "driver.hpp"
+#include "ms.hpp"
 
 namespace gg {
 
@@ -316,24 +317,6 @@ __global__ __launch_bounds__(kBlock) void k_msbc_backward(DevGraph g, int K, con
                 for (int w = 0; w < kBlock / kWave; w++) t += s_w[tid][w];
                 delta_vm[(size_t)vv * K + tid] = t;
             }
-        }
-        __syncthreads();
-    }
-}
-
-// ---- vertex-major (n x K) -> row-major (rows j0.. of a k x n output), tiled through LDS
-template <class TI, class TO>
-__global__ __launch_bounds__(kBlock) void k_ms_transpose(const TI *in, int n, int K, TO *out, int j0) {
-    __shared__ TI tile[64][65];
-    for (int v0 = blockIdx.x * 64; v0 < n; v0 += gridDim.x * 64) {
-        for (int i = threadIdx.x; i < 64 * K; i += kBlock) {
-            const int dv = i / K, j = i % K;
-            if (v0 + dv < n) tile[j][dv] = in[(size_t)(v0 + dv) * K + j];
-        }
-        __syncthreads();
-        for (int i = threadIdx.x; i < 64 * K; i += kBlock) {
-            const int j = i / 64, dv = i % 64;
-            if (v0 + dv < n) out[(size_t)(j0 + j) * n + v0 + dv] = (TO)tile[j][dv];
         }
         __syncthreads();
     }

@@ -150,6 +150,7 @@ size_t workspace_bytes(const Graph &g, int algo, int k) {
     if (k > 1) {
         b += 3 * n * 8;  // multi-source masks
         if (algo == GG_ALGO_BC) b += (size_t)k * n * 8 + n * 4;
+        if (algo == GG_ALGO_SSSP) b += (size_t)k * n * 4 + 2 * n * 4;
     }
     return b;
 }

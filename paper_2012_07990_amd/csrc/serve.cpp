@@ -1,11 +1,11 @@
 // Serving loop on the GPU: a serve::Core (admission + continuous batching)
-// driven by an executor that runs batches on its own HIP streams. BFS
-// queries of one graph are batched up to 64 into one bit-packed traversal,
-// BC queries up to 16; SSSP, CC and PageRank run one query per launch. Every
-// worker owns a default-priority stream, so batches of different graphs and
-// algorithms overlap on the device. A query whose schedule is a persistent
-// (fused) loop takes the device exclusively: its co-resident grid assumes
-// no other kernel occupies the compute units.
+// driven by an executor that runs batches on its own HIP streams. BFS and
+// SSSP queries of one graph are batched up to 64 (a bit-packed traversal; a
+// shared-bucket delta-stepping loop), BC queries up to 16; CC and PageRank
+// run one query per launch. Every worker owns a default-priority stream, so
+// batches of different graphs and algorithms overlap on the device. A batch
+// that runs a persistent (fused) loop takes the device exclusively: its
+// co-resident grid assumes no other kernel occupies the compute units.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -38,7 +38,9 @@ struct GpuExecutor : serve::Executor {
         for (auto s : streams) (void)hipStreamDestroy(s);
     }
 
-    int max_batch(int algo) const override { return algo == GG_ALGO_BFS ? 64 : algo == GG_ALGO_BC ? 16 : 1; }
+    int max_batch(int algo) const override {
+        return algo == GG_ALGO_BFS || algo == GG_ALGO_SSSP ? 64 : algo == GG_ALGO_BC ? 16 : 1;
+    }
 
     size_t result_bytes(int gid, int algo) const override {
         const size_t n = (size_t)graphs[gid]->n;
@@ -61,7 +63,9 @@ struct GpuExecutor : serve::Executor {
             if (t != G.tuned.end() && !t->second.first.s1.kernel_fusion) return t->second.first;
         }
         gg_schedule s = preset_schedule(algo, GG_PRESET_POWERLAW);
-        if (algo == GG_ALGO_SSSP) s.s1.delta = 64;
+        // wider buckets on sparse high-diameter graphs: fewer rounds, each of
+        // which costs a grid barrier, against some re-relaxed edges
+        if (algo == GG_ALGO_SSSP) s.s1.delta = G.m < 8ll * G.n ? 512 : 64;
         if (algo == GG_ALGO_SSSP && !G.has_weights) s = default_schedule();
         return s;
     }
@@ -72,7 +76,7 @@ struct GpuExecutor : serve::Executor {
         const size_t n = (size_t)G.n;
         const int k = (int)b.reqs.size();
         const gg_schedule s = schedule_for(b.gid, b.algo);
-        const bool fused = k == 1 && s.s1.kernel_fusion;
+        const bool fused = (k == 1 && s.s1.kernel_fusion) || (k > 1 && b.algo == GG_ALGO_SSSP);
         std::shared_lock<std::shared_mutex> shared(device, std::defer_lock);
         std::unique_lock<std::shared_mutex> exclusive(device, std::defer_lock);
         if (fused) exclusive.lock();
@@ -95,8 +99,10 @@ struct GpuExecutor : serve::Executor {
                 for (auto *r : b.reqs) srcs.push_back(r->src);
                 void *stage = nullptr;
                 GG_HIP(hipMallocAsync(&stage, (size_t)k * result_bytes(b.gid, b.algo), st));
-                if (b.algo == GG_ALGO_BFS) {
-                    msbfs_run(G, srcs.data(), k, s, (int32_t *)stage, st, nullptr);
+                unsigned long long overflow = 0;
+                if (b.algo == GG_ALGO_BFS || b.algo == GG_ALGO_SSSP) {
+                    if (b.algo == GG_ALGO_BFS) msbfs_run(G, srcs.data(), k, s, (int32_t *)stage, st, nullptr);
+                    else mssssp_run(G, srcs.data(), k, s, (int32_t *)stage, st, nullptr, &overflow);
                     for (int i = 0; i < k; i++)
                         GG_HIP(hipMemcpyAsync(b.reqs[i]->result, (int32_t *)stage + i * n, 4 * n,
                                               hipMemcpyDeviceToDevice, st));
@@ -111,6 +117,16 @@ struct GpuExecutor : serve::Executor {
                     }
                 }
                 GG_HIP(hipFreeAsync(stage, st));
+                GG_HIP(hipStreamSynchronize(st));
+                for (int i = 0; i < k; i++) {
+                    serve::Req *r = b.reqs[i];
+                    r->status = ((overflow >> i) & 1ull) ? GG_ERR_OVERFLOW : GG_OK;
+                    if (r->status != GG_OK) {
+                        (void)hipFree(r->result);
+                        r->result = nullptr;
+                    }
+                }
+                return;
             }
             GG_HIP(hipStreamSynchronize(st));
             for (auto *r : b.reqs) r->status = GG_OK;

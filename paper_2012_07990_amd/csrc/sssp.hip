@@ -225,7 +225,7 @@ static void sssp_fused(Ctx &c, Graph &G, Workspace &ws, int32_t src, const gg_si
     GG_CHECK_LAUNCH();
     c.launches++;
     fill_i32(c, ws.counters.p, 1, 1);
-    const int blocks = fused_grid(kern, 2, c.num_cus);
+    const int blocks = fused_grid_for(kern, G, c.num_cus);
     FusedSsspArgs a{g, dist, ws.q[0].p, ws.q[1].p, ws.aux_i32[0].p, ws.aux_i32[1].p, ws.counters.p, ws.tags.p,
                     ws.aux_i32[2].p, n, s.delta, prepare_barrier(c, ws, blocks), c.edge_counter};
     void *args[] = {&a};

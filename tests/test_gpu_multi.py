@@ -1,12 +1,12 @@
 """GPU parity for the batched multi-source forms: every row of gg_bfs_multi /
-gg_bc_multi is bit-identical to the single-source call with the same source
-(and therefore to the oracle for the integer outputs)."""
+gg_sssp_multi / gg_bc_multi is bit-identical to the single-source call with
+the same source (and therefore to the oracle for the integer outputs)."""
 import numpy as np
 import pytest
 
 import graphgen
 import paper_2012_07990_amd as gg
-from gpu_util import assert_int_equal, dev_graph, host_graph, oracle_bc, oracle_bfs
+from gpu_util import assert_int_equal, dev_graph, host_graph, oracle_bc, oracle_bfs, oracle_sssp
 
 pytestmark = pytest.mark.gpu
 
@@ -60,6 +60,48 @@ def test_bc_multi_bit_identical_to_single(name, k):
         assert (err <= 1e-4 * np.abs(ed) + 1e-6).all()
 
 
+@pytest.mark.parametrize("name", ["rmat12", "rmat14", "grid64", "star5000", "cliques", "isolated7", "single",
+                                  "path100k", "fullgrid34"])
+@pytest.mark.parametrize("k,delta", [(1, 64), (9, 1), (33, 16), (64, 512)])
+def test_sssp_multi_matches_oracle(name, k, delta):
+    G = dev_graph(name)
+    srcs = _sources(name, k, seed=13)
+    st = gg.Stats()
+    d = G.sssp_multi(srcs, gg.make_schedule(delta=delta), stats=st).cpu().numpy()
+    assert d.shape == (k, host_graph(name).n)
+    for i, s in enumerate(srcs):
+        assert_int_equal(d[i], oracle_sssp(name, int(s)), "sssp_multi row %d (delta %d)" % (i, delta))
+    assert st.fused == 1 and st.buckets >= 1
+    single = G.sssp(int(srcs[-1]), gg.make_schedule(lb="cm", delta=delta)).cpu().numpy()
+    assert np.array_equal(d[-1], single)
+
+
+def test_sssp_multi_duplicate_sources_and_empty():
+    G = dev_graph("grid64")
+    d = G.sssp_multi([0, 77, 0, 4095, 77], gg.make_schedule(delta=8)).cpu().numpy()
+    assert np.array_equal(d[0], d[2]) and np.array_equal(d[1], d[4])
+    for i, s in enumerate([0, 77, 4095]):
+        assert_int_equal(d[[0, 1, 3][i]], oracle_sssp("grid64", s))
+    assert G.sssp_multi([]).shape == (0, G.n)
+
+
+def test_sssp_multi_overflow_and_weights():
+    g = graphgen.path(4)
+    w = np.full(g.m, 999_999_999, dtype=np.uint32)
+    G = gg.Graph.from_csr(g.n, g.row_ptr, g.col, w)
+    with pytest.raises(gg.GGError) as e:
+        G.sssp_multi([1, 0], gg.make_schedule(delta=1 << 20))
+    assert e.value.status == gg.ERR_OVERFLOW
+    d = G.sssp_multi([1, 2], gg.make_schedule(delta=1 << 20)).cpu().numpy()
+    assert list(d[0]) == [999_999_999, 0, 999_999_999, 1_999_999_998]
+    assert list(d[1]) == [1_999_999_998, 999_999_999, 0, 999_999_999]
+    h = host_graph("rmat12")
+    G2 = gg.Graph.from_csr(h.n, h.row_ptr, h.col)
+    with pytest.raises(gg.GGError) as e:
+        G2.sssp_multi([0])
+    assert e.value.status == gg.ERR_INVALID_ARG
+
+
 def test_multi_argument_errors():
     G = dev_graph("rmat12")
     with pytest.raises(gg.GGError) as e:
@@ -68,6 +110,12 @@ def test_multi_argument_errors():
     with pytest.raises(gg.GGError) as e:
         G.bc_multi([0, G.n])
     assert e.value.status == gg.ERR_INVALID_ARG
+    with pytest.raises(gg.GGError) as e:
+        G.sssp_multi([-1])
+    assert e.value.status == gg.ERR_INVALID_ARG
+    with pytest.raises(gg.GGError) as e:
+        G.sssp_multi([0], gg.make_schedule(delta=0))
+    assert e.value.status in (gg.ERR_INVALID_ARG, gg.ERR_UNSUPPORTED_SCHEDULE)
 
 
 def test_bc_multi_overflow():

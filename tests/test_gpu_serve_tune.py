@@ -93,6 +93,41 @@ def test_serving_fused_schedule_runs_exclusively():
     srv.close()
 
 
+def test_serving_batches_sssp_and_reports_overflow_per_query():
+    G = dev_graph("grid64")
+    srv = gg.Server(budget_bytes=1 << 30, nstreams=2)
+    gid = srv.add_graph(G)
+    ts = [(s, srv.submit(gid, gg.ALGO_SSSP, s)) for s in range(0, 4096, 41)]
+    batched = 0
+    for s, t in ts:
+        out = np.empty(G.n, dtype=np.int32)
+        r = srv.wait(t, 60.0, out=out)
+        assert r["status"] == gg.OK
+        batched += r["batch_size"] > 1
+        assert_int_equal(out, oracle_sssp("grid64", s))
+    assert batched > 0
+    srv.close()
+    # path of 4 with huge weights: from vertex 0 the far end is beyond INT32_MAX-1,
+    # from vertex 1 every distance fits
+    g = graphgen.path(4)
+    H = gg.Graph.from_csr(g.n, g.row_ptr, g.col, np.full(g.m, 999_999_999, dtype=np.uint32))
+    srv = gg.Server(budget_bytes=1 << 30, nstreams=1)
+    gid = srv.add_graph(H)
+    ts = [(s, srv.submit(gid, gg.ALGO_SSSP, s)) for s in [0, 1, 3, 2, 0, 1]]
+    for s, t in ts:
+        out = np.empty(4, dtype=np.int32)
+        if s in (0, 3):
+            with pytest.raises(gg.GGError) as e:
+                srv.wait(t, 60.0, out=out)
+            assert e.value.status == gg.ERR_OVERFLOW
+            continue
+        r = srv.wait(t, 60.0, out=out)
+        assert r["status"] == gg.OK
+        if s == 1:
+            assert list(out) == [999_999_999, 0, 999_999_999, 1_999_999_998]
+    srv.close()
+
+
 def test_serving_small_budget_still_completes():
     G = dev_graph("rmat12")
     one = G.workspace_bytes(gg.ALGO_BFS, 1) + 4 * G.n
