@@ -53,6 +53,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--only", default="", help="comma list of algorithms to run (bfs,sssp,cc,pr,bc)")
     p.add_argument("--sweep", action="store_true", help="time every schedule family per algorithm")
+    p.add_argument("--sweep-filter", default="", help="comma list of substrings: only sweep schedules matching one")
     p.add_argument("--verbose", action="store_true")
     p.add_argument("--no-batched", action="store_true", help="skip the batched multi-source section")
     p.add_argument("--no-serving", action="store_true", help="skip the serving section")
@@ -61,6 +62,8 @@ def parse():
     p.add_argument("--serve-budget-s", type=float, default=150.0, help="wall-clock cap of the serving section")
     p.add_argument("--grid", type=int, default=0,
                    help="also time BFS/SSSP on a WxW road-like grid (fused vs unfused, delta sweep)")
+    p.add_argument("--grid-deltas", default="1,8,64,512",
+                   help="delta values of the grid SSSP runs (an unfused run is skipped when the fused one took > 20 s)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy three times (scales rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     p.add_argument("--serve-full", action="store_true",
@@ -75,11 +78,13 @@ def log(*a):
 def schedules(gg):
     """The schedule each algorithm runs in the step (chosen by sweeps on this graph family)."""
     bfs = gg.schedule_preset(gg.ALGO_BFS, gg.PRESET_POWERLAW)
+    bfs.s1.load_balance = gg.LB_STRICT
     bfs.threshold = 0.01
-    sssp = gg.make_schedule(lb="etwc", delta=64)
+    sssp = gg.make_schedule(lb="strict", delta=64)
     cc = gg.make_schedule(lb="etwc")
     pr = gg.make_schedule(lb="strict", direction=gg.PULL, edge_blocking=True, blocking_size=PR_SEGMENT)
     bc = gg.schedule_preset(gg.ALGO_BC, gg.PRESET_POWERLAW)
+    bc.s1.load_balance = gg.LB_STRICT
     bc.threshold = 0.01
     return {"bfs": bfs, "sssp": sssp, "cc": cc, "pr": pr, "bc": bc}
 
@@ -202,6 +207,8 @@ def main():
             if a not in algos:
                 continue
             for name, s in d.items():
+                if args.sweep_filter and not any(f in name for f in args.sweep_filter.split(",")):
+                    continue
                 try:
                     run(a, s)
                     torch.cuda.synchronize()
@@ -233,6 +240,13 @@ def main():
         ms = 1e3 * sorted(ts)[len(ts) // 2]
         per[a] = {"ms": round(ms, 4), "gteps": round(edges[a] / ms / 1e6, 3), "iterations": st.iterations,
                   "launches": st.launches}
+        # work done (outside the timing): edges the traversal examined
+        sc = gg.Stats()
+        sc.flags = gg.STATS_COUNT_EDGES
+        run(a, scheds[a], sc)
+        torch.cuda.synchronize()
+        per[a]["edges_examined"] = int(sc.edges_examined)
+        per[a]["vertices_processed"] = int(sc.vertices_processed)
         log("algo %-5s %9.3f ms  %8.2f GTEPS  (%s)" % (a, ms, edges[a] / ms / 1e6, st.as_dict()))
 
     # the timed steps
@@ -290,7 +304,8 @@ def main():
     G.close()
     del G
 
-    grid = grid_section(gg, graphgen, torch, args.grid) if args.grid else None
+    grid = grid_section(gg, graphgen, torch, args.grid, [int(x) for x in args.grid_deltas.split(",")]) \
+        if args.grid else None
     batched = None if args.no_batched else batched_section(gg, graphgen, torch)
     serving = None if args.no_serving else serving_section(gg, graphgen, torch, args)
 
@@ -312,16 +327,21 @@ def main():
     print(json.dumps(rec), flush=True)
 
 
-def grid_section(gg, graphgen, torch, W):
-    """High-diameter road-like grid: SSSP over delta in {1, 8, 64, 512} and BFS,
-    each fused (one persistent launch) and unfused (one launch per round)."""
+def grid_section(gg, graphgen, torch, W, deltas):
+    """High-diameter road-like grid: SSSP over the given deltas and BFS, each
+    fused (one persistent launch) and unfused (one launch per round; skipped
+    when the fused run already took over 20 s)."""
     g = graphgen.grid(W)
     G = gg.Graph.from_graphgen(g)
     out = {"workload": "grid %dx%d, 10%% non-tree edges dropped, weights 1..999, source 0" % (W, W),
            "n": g.n, "m": g.m, "runs": []}
     for algo in ["bfs", "sssp"]:
-        for delta in ([1, 8, 64, 512] if algo == "sssp" else [0]):
+        for delta in (deltas if algo == "sssp" else [0]):
+            fused_ms = 0.0
             for fused in (True, False):
+                if not fused and fused_ms > 20000:
+                    log("grid: %s delta %d unfused skipped (fused run took %.1f s)" % (algo, delta, fused_ms / 1e3))
+                    continue
                 sch = gg.make_schedule(lb="cm", delta=max(delta, 1), fusion=fused)
                 run = (lambda: G.sssp(0, sch, stats=st)) if algo == "sssp" else (lambda: G.bfs(0, sch, stats=st))
                 st = gg.Stats()
@@ -340,6 +360,8 @@ def grid_section(gg, graphgen, torch, W):
                        "us_per_round": round(1e3 * ms / max(st.iterations, 1), 2)}
                 log("grid: %s" % rec)
                 out["runs"].append(rec)
+                if fused:
+                    fused_ms = ms
     G.close()
     return out
 
@@ -348,7 +370,7 @@ def batched_section(gg, graphgen, torch):
     """64 BFS + 16 BC sources on R-MAT 20 in one batched call each, against the
     same sources as single-source calls (bit-identity checked on the way)."""
     import numpy as np
-    g = graphgen.rmat(20)
+    g = graphgen.rmat(20, weights=True)
     G = gg.Graph.from_graphgen(g)
     deg = g.degrees()
     bfs_src = graphgen.sample_sources(g, 64, 7)
@@ -369,7 +391,7 @@ def batched_section(gg, graphgen, torch):
             ts.append(time.perf_counter() - t1)
         return sorted(ts)[len(ts) // 2]
 
-    d_multi = G.bfs_multi(bfs_src)
+    d_multi = G.bfs_multi(bfs_src, sb)
     s_multi, dl_multi = G.bc_multi(bc_src)
     ok = True
     for i in range(0, 64, 9):
@@ -378,7 +400,7 @@ def batched_section(gg, graphgen, torch):
         s1, d1 = G.bc(int(bc_src[i]), sc)
         ok &= bool(torch.equal(s_multi[i], s1)) and bool(torch.equal(dl_multi[i].view(torch.int32),
                                                                         d1.view(torch.int32)))
-    t_multi = timed(lambda: (G.bfs_multi(bfs_src), G.bc_multi(bc_src)))
+    t_multi = timed(lambda: (G.bfs_multi(bfs_src, sb), G.bc_multi(bc_src)))
     t_single = timed(lambda: ([G.bfs(int(x), sb) for x in bfs_src], [G.bc(int(x), sc) for x in bc_src]), reps=1)
     reach = d_multi.cpu().numpy() >= 0
     edges = float(sum(deg[reach[i]].sum() for i in range(64)))
@@ -412,6 +434,24 @@ def batched_section(gg, graphgen, torch):
                "queries_per_s": round(64 / t_m, 1), "bit_identical": ok_s}
         log("batched sssp: %s" % rec)
         out["sssp"].append(rec)
+        if name.startswith("grid"):
+            # 64 BFS sources on the grid: the push loop against the pull sweep
+            # and against single fused BFS calls (4 timed, scaled to 64)
+            bs = gg.make_schedule(lb="cm", fusion=True)
+            pull = gg.make_schedule(direction=gg.PULL)
+            st = gg.Stats()
+            dp = Gx.bfs_multi(srcs, gg.make_schedule(), stats=st)
+            ok_b = bool(torch.equal(dp, Gx.bfs_multi(srcs, pull)))
+            ok_b &= all(bool(torch.equal(dp[i], Gx.bfs(int(srcs[i]), bs))) for i in range(0, 64, 21))
+            t_push = timed(lambda: Gx.bfs_multi(srcs, gg.make_schedule()), reps=1)
+            t_pull = timed(lambda: Gx.bfs_multi(srcs, pull), reps=1)
+            t_1 = timed(lambda: [Gx.bfs(int(x), bs) for x in srcs[:4]], reps=1) * 16
+            rec = {"graph": name, "k": 64, "ms_push_batched": round(t_push * 1e3, 3),
+                   "ms_pull_batched": round(t_pull * 1e3, 3), "ms_single_calls": round(t_1 * 1e3, 3),
+                   "single_calls_timed": 4, "speedup": round(t_1 / min(t_push, t_pull), 2), "levels": st.iterations,
+                   "queries_per_s": round(64 / min(t_push, t_pull), 1), "bit_identical": ok_b}
+            log("batched bfs: %s" % rec)
+            out["grid_bfs"] = rec
         Gx.close()
     return out
 

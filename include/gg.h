@@ -220,8 +220,13 @@ gg_status gg_bc(gg_graph *g, int32_t src, const gg_schedule *s, uint64_t *sigma_
                 float *delta_dev, gg_stream_t stream, gg_stats *stats);
 
 /* ---- batched multi-source --------------------------------------------------------------- */
-/* k <= 64 sources (host array) in one bit-packed traversal; depth_dev is k x n
-   row-major. Bit-identical to k gg_bfs calls. */
+/* k <= 64 sources (host array) in one batched traversal; depth_dev is k x n
+   row-major. The schedule picks the form (configDirection): PUSH without a
+   hybrid switch runs a sparse-queue loop in one persistent launch (one grid
+   barrier per level, work proportional to the frontier: high-diameter
+   graphs); PULL or hybrid runs a bit-packed PULL sweep per level (every
+   edge's column and frontier word read once for all sources: low-diameter
+   graphs). Bit-identical to k gg_bfs calls. */
 gg_status gg_bfs_multi(gg_graph *g, const int32_t *srcs_host, int32_t k, const gg_schedule *s,
                        int32_t *depth_dev, gg_stream_t stream, gg_stats *stats);
 /* k <= 64 delta-stepping SSSP sources (host array) sharing one bucket loop

@@ -22,6 +22,8 @@ void msbfs_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &s, int32
                gg_stats *st);
 // overflow_mask: when non-null, receives the sources whose distances overflow
 // (instead of an exception)
+// batched BFS as the unit-weight form of the batched delta-stepping loop
+void msbfs_push_run(Graph &G, const int32_t *srcs, int k, int32_t *depth, hipStream_t stream, gg_stats *st);
 void mssssp_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &s, int32_t *dist, hipStream_t stream,
                 gg_stats *st, unsigned long long *overflow_mask);
 size_t mssssp_work_bytes(const Graph &G, int k);

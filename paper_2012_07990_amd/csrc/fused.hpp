@@ -81,14 +81,15 @@ __device__ __forceinline__ bool grid_sync(GridBarrier &b) {
     return s_abort == 0;
 }
 
-// Co-resident grid for a persistent kernel: `per_cu` workgroups per compute
-// unit, capped by the occupancy the kernel actually achieves.
-int fused_grid(const void *kernel, int per_cu, int num_cus);
+// Co-resident grid for a persistent kernel: `per_cu` workgroups (of
+// `threads` lanes) per compute unit, capped by the occupancy the kernel
+// actually achieves; per_cu <= 0 asks for one workgroup per two units.
+int fused_grid(const void *kernel, int per_cu, int num_cus, int threads = kBlock);
 int fused_grid_for(const void *kernel, const Graph &G, int num_cus);
 
 // Launch with the cooperative API (which refuses grids that cannot be
 // co-resident).
-void launch_cooperative(Ctx &c, const void *kernel, int blocks, void **args);
+void launch_cooperative(Ctx &c, const void *kernel, int blocks, void **args, int threads = kBlock);
 
 // Allocate/zero the barrier words in the workspace for a grid of `blocks`.
 GridBarrier prepare_barrier(Ctx &c, Workspace &ws, int blocks);

@@ -329,6 +329,7 @@ __device__ void lb_strict(const DevGraph &g, const Src &src, const long long *sc
                           const OutFrontier &out, Tid t, long long &ne) {
     constexpr int W = kStrictChunk;
     __shared__ long long s_scan[W + 1];
+    __shared__ int s_u[W], s_beg[W];  // the window's sources and their row starts
     __shared__ int s_k0, s_k1;
     const long long total = scan[src.size];
     const long long nchunks = (total + W - 1) / W;
@@ -347,19 +348,27 @@ __device__ void lb_strict(const DevGraph &g, const Src &src, const long long *sc
         __syncthreads();
         for (int kw = k0; kw <= k1; kw += W) {  // LDS windows of sources [kw, kw+W)
             const int wlen = (k1 - kw + 1 < W) ? k1 - kw + 1 : W;
-            for (int j = threadIdx.x; j <= wlen; j += kBlock) s_scan[j] = scan[kw + j];
+            for (int j = threadIdx.x; j <= wlen; j += kBlock) {
+                s_scan[j] = scan[kw + j];
+                if (j < wlen && kw + j < src.size) {
+                    const int u = src.get(kw + j);
+                    s_u[j] = u;
+                    s_beg[j] = g.row_ptr[u];
+                }
+            }
             __syncthreads();
             long long lo = s_scan[0] > r0 ? s_scan[0] : r0;
             long long hi = s_scan[wlen] < r1 ? s_scan[wlen] : r1;
+            int a = 0;  // owners only move forward as r grows
             for (long long r = lo + threadIdx.x; r < hi; r += kBlock) {
-                int a = 0, b = wlen;  // last j with s_scan[j] <= r
+                int b = wlen;  // last j with s_scan[j] <= r
                 while (b - a > 1) {
                     const int mid = (a + b) >> 1;
                     if (s_scan[mid] <= r) a = mid; else b = mid;
                 }
-                const int u = src.get(kw + a);
+                const int u = s_u[a];
                 if (f.done(u)) continue;
-                const int e = g.row_ptr[u] + (int)(r - s_scan[a]);
+                const int e = s_beg[a] + (int)(r - s_scan[a]);
                 const int x = f.edge(u, g.col[e], e);
                 emit<CREATE, DEDUP>(out, x >= 0, x);
                 ne++;

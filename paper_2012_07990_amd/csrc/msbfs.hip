@@ -335,8 +335,14 @@ static MsBuffers ms_buffers(Workspace &ws, int n, int K) {
     return MsBuffers{ws.aux_u64[0].p, ws.aux_u64[1].p, ws.aux_u64[2].p, ws.aux_i32[3].p};
 }
 
-void msbfs_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &, int32_t *depth, hipStream_t stream,
+void msbfs_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &sch, int32_t *depth, hipStream_t stream,
                gg_stats *st) {
+    // PUSH without a hybrid switch: the sparse-queue loop (one barrier per
+    // level); otherwise the bit-packed PULL sweep below
+    if (!sch.hybrid && sch.s1.direction == GG_PUSH) {
+        msbfs_push_run(G, srcs, k, depth, stream, st);
+        return;
+    }
     Ctx c;
     c.s = stream;
     c.num_cus = G.num_cus;

@@ -22,10 +22,20 @@
 // those bits move to the near set, later ones stay, and bits whose distance
 // fell back into a settled bucket are dropped.
 //
-// Work in a round is spread like CM (one workgroup per 256 queue entries):
-// an exclusive scan of popcount(word) * degree gives every (edge, source)
-// pair a rank, lanes stride over the ranks, and the sources of one edge sit
-// on neighbouring lanes, so their distance words share cache lines.
+// With unit weights and an unbounded bucket every improvement joins the next
+// round, so a round is one BFS level: the same loop is the PUSH form of the
+// batched BFS (one barrier per level, work proportional to the frontier),
+// which suits high-diameter graphs where the bit-packed PULL sweep would
+// scan every vertex once per level.
+//
+// Work in a round is spread like CM (one workgroup per kMsBlock queue
+// entries): an exclusive scan of popcount(word) * degree gives every (edge,
+// source) pair a rank, lanes stride over the ranks, and the sources of one
+// edge sit on neighbouring lanes, so their distance words share cache lines.
+// The loop is bound by the latency of its dependent accesses (entry, row
+// range, column, distance, atomic, append), so it runs few, wide workgroups:
+// many waves in flight per compute unit while the grid barrier, whose cost
+// grows with the number of workgroups, stays cheap.
 #include <climits>
 
 #include "algos.hpp"
@@ -36,6 +46,8 @@
 namespace gg {
 
 using u64 = unsigned long long;
+
+constexpr int kMsBlock = 1024;  // lanes per workgroup of the batched loop
 
 // index of the i-th set bit of m (i < popcount(m)), by halving the window
 __device__ __forceinline__ int select_bit(u64 m, int i) {
@@ -56,7 +68,7 @@ __device__ __forceinline__ long long block_excl_scan64(long long x, long long &e
     __syncthreads();
     long long off = 0, total = 0;
 #pragma unroll
-    for (int w = 0; w < kBlock / kWave; w++) {
+    for (int w = 0; w < kMsBlock / kWave; w++) {
         const long long v = s_tmp[w];
         if (w < wib) off += v;
         total += v;
@@ -113,57 +125,93 @@ __global__ __launch_bounds__(kBlock) void k_mssssp_init(int n, int K, const int3
     }
 }
 
+// relax one (edge, source) pair; every active lane of the wave calls the
+// appends together
+template <bool UNIT>
+__device__ __forceinline__ void ms_relax_pair(const MsSsspArgs &a, int du, int e, int v, int src, u64 *nnext,
+                                              int32_t *qout, int32_t *qcount, int32_t *farq, int32_t *farc,
+                                              long long bucket_end) {
+    const long long nd = (long long)du + (UNIT ? 1ll : (long long)a.g.w[e]);
+    int32_t *dv = &a.dist[(size_t)v * a.K + src];
+    bool to_near = false, to_far = false;
+    if (nd > (long long)INT_MAX - 1) {
+        if (*dv == INT_MAX) a.ctr[10] = 1;  // confirmed after the loop
+    } else if (nd < *dv) {
+        const int old = atomic_min_i32(dv, (int)nd);
+        if (nd < old) {
+            const u64 bit = 1ull << src;
+            if (nd < bucket_end) to_near = atomic_or_u64(&nnext[v], bit) == 0;
+            else to_far = atomic_or_u64(&a.far[v], bit) == 0;
+        }
+    }
+    wave_append(qout, qcount, a.g.n, a.ctr + 12, to_near, v);
+    wave_append(farq, farc, a.g.n, a.ctr + 12, to_far, v);
+}
+
+// In a full round (a workgroup's share of the queue is at least kMsBlock
+// entries) entries with at most kMsLaneWork (edge, source) pairs are relaxed
+// by their own lane and larger ones are spread over the workgroup by rank. A
+// smaller round is divided evenly over all workgroups and every entry's pairs
+// are spread by rank, so that each lane holds about one pair: such rounds are
+// bound by the latency of one relaxation, not by throughput.
+constexpr int kMsLaneWork = 32;
+
 // one round: relax the (edge, source) pairs of the near queue
+template <bool UNIT>
 __device__ __forceinline__ void ms_relax(const MsSsspArgs &a, const int32_t *qin, int cnt, u64 *ncur, u64 *nnext,
                                          int32_t *qout, int32_t *qcount, int32_t *farq, int32_t *farc,
                                          long long bucket_end, Tid t) {
-    __shared__ long long s_scan[kBlock + 1], s_tmp[kBlock / kWave];
-    __shared__ int s_u[kBlock], s_beg[kBlock], s_p[kBlock];
-    __shared__ u64 s_m[kBlock];
-    const int K = a.K, n = a.g.n;
-    int32_t *flags = a.ctr + 10;
-    for (int base = t.block * kBlock; base < cnt; base += t.nblocks * kBlock) {
+    __shared__ long long s_scan[kMsBlock + 1], s_tmp[kMsBlock / kWave];
+    __shared__ int s_u[kMsBlock], s_beg[kMsBlock], s_p[kMsBlock];
+    __shared__ u64 s_m[kMsBlock];
+    const int K = a.K;
+    const int share = (cnt + t.nblocks - 1) / t.nblocks;
+    const int chunk = share < kMsBlock ? share : kMsBlock;  // entries per workgroup step (uniform)
+    const bool full = chunk == kMsBlock;
+    for (int base = t.block * chunk; base < cnt; base += t.nblocks * chunk) {
         const int i = base + (int)threadIdx.x;
-        int u = 0, beg = 0, p = 0;
+        int u = 0, beg = 0, end = 0, p = 0;
         u64 m = 0;
         long long work = 0;
-        if (i < cnt) {
+        if ((int)threadIdx.x < chunk && i < cnt) {
             u = qin[i];
             m = ncur[u];
             ncur[u] = 0;  // only this entry reads or clears it in this round
             p = __popcll(m);
             beg = a.g.row_ptr[u];
-            work = (long long)p * (a.g.row_ptr[u + 1] - beg);
+            end = a.g.row_ptr[u + 1];
+            work = (long long)p * (end - beg);
         }
+        const bool own = full && work <= kMsLaneWork;
+        // small entries: this lane walks its edges, and per edge its sources
+        if (own) {
+            for (int e = beg; e < end; e++) {
+                const int v = a.g.col[e];
+                u64 mm = m;
+                while (mm) {
+                    const int src = __ffsll(mm) - 1;
+                    mm &= mm - 1;
+                    ms_relax_pair<UNIT>(a, a.dist[(size_t)u * K + src], e, v, src, nnext, qout, qcount, farq, farc,
+                                        bucket_end);
+                }
+            }
+        }
+        // large entries: ranks over the workgroup, sources of an edge on adjacent lanes
         long long excl;
-        const long long total = block_excl_scan64(work, excl, s_tmp);
+        const long long total = block_excl_scan64(own ? 0 : work, excl, s_tmp);
+        if (total == 0) continue;  // uniform: every lane read the same total
         s_u[threadIdx.x] = u; s_beg[threadIdx.x] = beg; s_p[threadIdx.x] = p; s_m[threadIdx.x] = m;
         s_scan[threadIdx.x] = excl;
         __syncthreads();
-        for (long long j = threadIdx.x; j < total; j += kBlock) {
-            const int o = last_le64(s_scan, kBlock, j);
+        for (long long j = threadIdx.x; j < total; j += kMsBlock) {
+            const int o = last_le64(s_scan, chunk, j);
             const unsigned r = (unsigned)(j - s_scan[o]);
             const unsigned po = (unsigned)s_p[o];
             const unsigned el = r / po;
             const int src = select_bit(s_m[o], (int)(r - el * po));
             const int e = s_beg[o] + (int)el;
-            const int v = a.g.col[e];
-            const int du = a.dist[(size_t)s_u[o] * K + src];
-            const long long nd = (long long)du + (long long)a.g.w[e];
-            int32_t *dv = &a.dist[(size_t)v * K + src];
-            bool to_near = false, to_far = false;
-            if (nd > (long long)INT_MAX - 1) {
-                if (*dv == INT_MAX) flags[0] = 1;  // confirmed after the loop
-            } else if (nd < *dv) {
-                const int old = atomic_min_i32(dv, (int)nd);
-                if (nd < old) {
-                    const u64 bit = 1ull << src;
-                    if (nd < bucket_end) to_near = atomic_or_u64(&nnext[v], bit) == 0;
-                    else to_far = atomic_or_u64(&a.far[v], bit) == 0;
-                }
-            }
-            wave_append(qout, qcount, n, a.ctr + 12, to_near, v);
-            wave_append(farq, farc, n, a.ctr + 12, to_far, v);
+            ms_relax_pair<UNIT>(a, a.dist[(size_t)s_u[o] * K + src], e, a.g.col[e], src, nnext, qout, qcount, farq,
+                                farc, bucket_end);
         }
         __syncthreads();
     }
@@ -173,7 +221,7 @@ __device__ __forceinline__ void ms_relax(const MsSsspArgs &a, const int32_t *qin
 __device__ __forceinline__ void ms_far_min(const MsSsspArgs &a, const int32_t *farq, int fc, int k, int32_t *kmin,
                                            Tid t) {
     int local = INT_MAX;
-    for (int i = t.block * kBlock + (int)threadIdx.x; i < fc; i += t.nblocks * kBlock) {
+    for (int i = t.block * kMsBlock + (int)threadIdx.x; i < fc; i += t.nblocks * kMsBlock) {
         const int v = farq[i];
         u64 m = a.far[v];
         while (m) {
@@ -195,10 +243,10 @@ __device__ __forceinline__ void ms_far_min(const MsSsspArgs &a, const int32_t *f
 __device__ __forceinline__ void ms_far_split(const MsSsspArgs &a, const int32_t *farq, int fc, int knew,
                                              u64 *nnext, int32_t *qout, int32_t *qcount, int32_t *nfarq,
                                              int32_t *nfarc, Tid t) {
-    const int stride = t.nblocks * kBlock;
+    const int stride = t.nblocks * kMsBlock;
     const int n_iter = (fc + stride - 1) / stride;
     for (int it = 0; it < n_iter; it++) {
-        const int i = it * stride + t.block * kBlock + (int)threadIdx.x;
+        const int i = it * stride + t.block * kMsBlock + (int)threadIdx.x;
         u64 move = 0, keep = 0;
         int v = 0;
         if (i < fc) {
@@ -219,7 +267,8 @@ __device__ __forceinline__ void ms_far_split(const MsSsspArgs &a, const int32_t 
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_mssssp_fused(MsSsspArgs a) {
+template <bool UNIT>
+__global__ __launch_bounds__(kMsBlock) void k_mssssp_fused(MsSsspArgs a) {
     const Tid t = Tid::here();
     GridBarrier bar = a.bar;
     int r = 0, k = 0, fe = 0, adv = 0, rounds = 0;
@@ -237,7 +286,8 @@ __global__ __launch_bounds__(kBlock) void k_mssssp_fused(MsSsspArgs a) {
         int32_t *farq = (fe & 1) ? a.farq1 : a.farq0;
         int32_t *farc = a.ctr + 3 + (fe & 1);
         if (cnt > 0) {
-            ms_relax(a, qin, cnt, ncur, nnext, qout, qcount, farq, farc, (long long)(k + 1) * a.delta, t);
+            const long long bucket_end = UNIT ? LLONG_MAX : (long long)(k + 1) * a.delta;
+            ms_relax<UNIT>(a, qin, cnt, ncur, nnext, qout, qcount, farq, farc, bucket_end, t);
             rounds++;
         } else {
             const int fc = min(load_relaxed(farc), a.g.n);
@@ -288,19 +338,39 @@ size_t mssssp_work_bytes(const Graph &G, int k) {
     return n * (size_t)k * 4 + n * 8 * 3 + n * 4 * 4;
 }
 
-void mssssp_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &sch, int32_t *dist, hipStream_t stream,
-                gg_stats *st, unsigned long long *overflow_mask) {
+// vertex-major distances -> k x n row-major; unreached becomes `unreached`
+__global__ __launch_bounds__(kBlock) void k_ms_dist_out(const int32_t *in, int n, int K, int32_t *out,
+                                                        int32_t unreached) {
+    __shared__ int32_t tile[64][65];
+    for (int v0 = blockIdx.x * 64; v0 < n; v0 += gridDim.x * 64) {
+        for (int i = threadIdx.x; i < 64 * K; i += kBlock) {
+            const int dv = i / K, j = i % K;
+            if (v0 + dv < n) tile[j][dv] = in[(size_t)(v0 + dv) * K + j];
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < 64 * K; i += kBlock) {
+            const int j = i / 64, dv = i % 64;
+            if (v0 + dv < n) {
+                const int32_t x = tile[j][dv];
+                out[(size_t)j * n + v0 + dv] = x == INT_MAX ? unreached : x;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// The shared loop: UNIT = true is the batched PUSH BFS (depth, -1 unreached),
+// false the batched SSSP (distance, INT32_MAX unreached).
+static void ms_push_loop(Graph &G, const int32_t *srcs, int k, bool unit, int delta, int32_t *out,
+                         hipStream_t stream, gg_stats *st, unsigned long long *overflow_mask) {
     Ctx c;
     c.s = stream;
     c.num_cus = G.num_cus;
     StatsScope scope(st, c);
     if (overflow_mask) *overflow_mask = 0;
     if (k == 0) { scope.finish(); return; }
-    require(G.has_weights, GG_ERR_INVALID_ARG, "SSSP needs edge weights");
     require((long long)G.max_degree * 64 < (1ll << 31), GG_ERR_UNSUPPORTED_SCHEDULE,
-            "batched SSSP needs max degree below 2^25");
-    const int delta = sch.s1.delta;
-    require(delta >= 1, GG_ERR_INVALID_ARG, "delta must be >= 1");
+            "batched push traversal needs max degree below 2^25");
     Lease ws(G);
     const DevGraph g = G.view();
     const int n = g.n;
@@ -328,26 +398,30 @@ void mssssp_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &sch, in
                        near0, near1, far, ws->q[0].p, ctr, ctr + 12);
     GG_CHECK_LAUNCH();
     c.launches++;
-    const void *kern = (const void *)k_mssssp_fused;
-    const int blocks = fused_grid_for(kern, G, c.num_cus);
+    const void *kern = unit ? (const void *)k_mssssp_fused<true> : (const void *)k_mssssp_fused<false>;
+    // wide workgroups: one per compute unit on dense graphs, one per two units
+    // on sparse ones, whose rounds are smaller and pay relatively more for the
+    // barrier
+    const bool sparse = G.m < 8ll * (long long)G.n;
+    const int blocks = fused_grid(kern, sparse ? 0 : 1, c.num_cus, kMsBlock);
     MsSsspArgs a{g, k, dist_vm, near0, near1, far, ws->q[0].p, ws->q[1].p, ws->aux_i32[0].p, ws->aux_i32[1].p,
-                 ctr, delta, prepare_barrier(c, *ws, blocks)};
+                 ctr, unit ? INT_MAX : delta, prepare_barrier(c, *ws, blocks)};
     void *args[] = {&a};
-    launch_cooperative(c, kern, blocks, args);
+    launch_cooperative(c, kern, blocks, args, kMsBlock);
     check_barrier(c, *ws);
     GG_HIP(hipMemcpyAsync(ws->h_i32.p, ctr, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
     GG_HIP(hipStreamSynchronize(c.s));
     const int32_t *h = ws->h_i32.p;
-    require(h[12] == 0, GG_ERR_OUT_OF_MEMORY, "batched SSSP queue overflow");
-    const int maybe_overflow = h[10];
+    require(h[12] == 0, GG_ERR_OUT_OF_MEMORY, "batched traversal queue overflow");
+    const int maybe_overflow = unit ? 0 : h[10];
     if (st) {
         st->fused = 1;
         st->iterations = h[8];
         st->push_iterations = h[8];
-        st->buckets = h[9];
+        st->buckets = unit ? 0 : h[9];
     }
-    hipLaunchKernelGGL((k_ms_transpose<int32_t, int32_t>), dim3(blocks_for(n, 64, 16384)), dim3(kBlock), 0, c.s,
-                       dist_vm, n, k, dist, 0);
+    hipLaunchKernelGGL(k_ms_dist_out, dim3(blocks_for(n, 64, 16384)), dim3(kBlock), 0, c.s, dist_vm, n, k, out,
+                       unit ? -1 : INT_MAX);
     GG_CHECK_LAUNCH();
     c.launches++;
     u64 bad = 0;
@@ -365,6 +439,17 @@ void mssssp_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &sch, in
     scope.finish();
     if (overflow_mask) *overflow_mask = bad;
     else require(bad == 0, GG_ERR_OVERFLOW, "a shortest-path distance exceeds INT32_MAX-1");
+}
+
+void mssssp_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &sch, int32_t *dist, hipStream_t stream,
+                gg_stats *st, unsigned long long *overflow_mask) {
+    require(G.has_weights, GG_ERR_INVALID_ARG, "SSSP needs edge weights");
+    require(sch.s1.delta >= 1, GG_ERR_INVALID_ARG, "delta must be >= 1");
+    ms_push_loop(G, srcs, k, false, sch.s1.delta, dist, stream, st, overflow_mask);
+}
+
+void msbfs_push_run(Graph &G, const int32_t *srcs, int k, int32_t *depth, hipStream_t stream, gg_stats *st) {
+    ms_push_loop(G, srcs, k, true, 0, depth, stream, st, nullptr);
 }
 
 }  // namespace gg

@@ -1,11 +1,14 @@
 // Serving loop on the GPU: a serve::Core (admission + continuous batching)
 // driven by an executor that runs batches on its own HIP streams. BFS and
-// SSSP queries of one graph are batched up to 64 (a bit-packed traversal; a
-// shared-bucket delta-stepping loop), BC queries up to 16; CC and PageRank
-// run one query per launch. Every worker owns a default-priority stream, so
-// batches of different graphs and algorithms overlap on the device. A batch
-// that runs a persistent (fused) loop takes the device exclusively: its
-// co-resident grid assumes no other kernel occupies the compute units.
+// SSSP queries of one graph are batched up to 64, BC queries up to 16; CC
+// and PageRank run one query per launch. Batched SSSP is a shared-bucket
+// delta-stepping loop; batched BFS is the bit-packed PULL sweep on
+// low-diameter graphs and the unit-weight form of the SSSP loop on sparse,
+// high-diameter ones, where single queries take the batched loops too (they
+// are persistent). Every worker owns a default-priority stream, so batches of
+// different graphs and algorithms overlap on the device. A batch that runs a
+// persistent (fused) loop takes the device exclusively: its co-resident grid
+// assumes no other kernel occupies the compute units.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -63,6 +66,10 @@ struct GpuExecutor : serve::Executor {
             if (t != G.tuned.end() && !t->second.first.s1.kernel_fusion) return t->second.first;
         }
         gg_schedule s = preset_schedule(algo, GG_PRESET_POWERLAW);
+        // STRICT push measured fastest on R-MAT for BFS, SSSP and BC
+        if (algo == GG_ALGO_BFS || algo == GG_ALGO_SSSP || algo == GG_ALGO_BC) s.s1.load_balance = GG_LB_STRICT;
+        // high-diameter graphs: batched BFS as the sparse-queue push loop
+        if (algo == GG_ALGO_BFS && G.m < 8ll * G.n) s = default_schedule();
         // wider buckets on sparse high-diameter graphs: fewer rounds, each of
         // which costs a grid barrier, against some re-relaxed edges
         if (algo == GG_ALGO_SSSP) s.s1.delta = G.m < 8ll * G.n ? 512 : 64;
@@ -76,14 +83,18 @@ struct GpuExecutor : serve::Executor {
         const size_t n = (size_t)G.n;
         const int k = (int)b.reqs.size();
         const gg_schedule s = schedule_for(b.gid, b.algo);
-        const bool fused = (k == 1 && s.s1.kernel_fusion) || (k > 1 && b.algo == GG_ALGO_SSSP);
+        // the batched loops also serve single queries where they are persistent
+        // push loops (SSSP always; BFS under a plain PUSH schedule)
+        const bool ms_push = b.algo == GG_ALGO_SSSP || (b.algo == GG_ALGO_BFS && !s.hybrid && s.s1.direction == GG_PUSH);
+        const bool batched = k > 1 || (ms_push && G.m < 8ll * G.n);
+        const bool fused = batched ? ms_push : s.s1.kernel_fusion;
         std::shared_lock<std::shared_mutex> shared(device, std::defer_lock);
         std::unique_lock<std::shared_mutex> exclusive(device, std::defer_lock);
         if (fused) exclusive.lock();
         else shared.lock();
         try {
             for (serve::Req *r : b.reqs) GG_HIP(hipMallocAsync(&r->result, r->result_bytes, st));
-            if (k == 1) {
+            if (!batched) {
                 serve::Req *r = b.reqs[0];
                 switch (b.algo) {
                 case GG_ALGO_BFS: bfs_run(G, r->src, s, (int32_t *)r->result, st, nullptr); break;

@@ -19,26 +19,41 @@ def _sources(name, k, seed=7):
     return s
 
 
+def _ms_sched(form):
+    if form == "push":
+        return gg.make_schedule()
+    if form == "pull":
+        return gg.make_schedule(direction=gg.PULL)
+    s = gg.schedule_preset(gg.ALGO_BFS, gg.PRESET_POWERLAW)
+    s.threshold = 0.01
+    return s
+
+
 @pytest.mark.parametrize("name", ["rmat12", "rmat14", "grid64", "star5000", "cliques", "isolated7", "single",
                                   "path100k"])
 @pytest.mark.parametrize("k", [1, 7, 64])
-def test_bfs_multi_matches_single_and_oracle(name, k):
+@pytest.mark.parametrize("form", ["push", "pull", "hybrid"])
+def test_bfs_multi_matches_single_and_oracle(name, k, form):
     G = dev_graph(name)
     srcs = _sources(name, k)
-    d = G.bfs_multi(srcs).cpu().numpy()
+    st = gg.Stats()
+    d = G.bfs_multi(srcs, _ms_sched(form), stats=st).cpu().numpy()
     assert d.shape == (k, host_graph(name).n)
+    assert st.fused == (1 if form == "push" else 0)
     for i, s in enumerate(srcs):
         assert_int_equal(d[i], oracle_bfs(name, int(s)), "bfs_multi row %d" % i)
     single = G.bfs(int(srcs[0]), gg.make_schedule(lb="etwc")).cpu().numpy()
     assert np.array_equal(d[0], single)
 
 
-def test_bfs_multi_duplicate_sources():
+@pytest.mark.parametrize("form", ["push", "pull"])
+def test_bfs_multi_duplicate_sources(form):
     G = dev_graph("rmat12")
     s = [5, 5, 9, 5]
-    d = G.bfs_multi(s).cpu().numpy()
+    d = G.bfs_multi(s, _ms_sched(form)).cpu().numpy()
     assert np.array_equal(d[0], d[1]) and np.array_equal(d[0], d[3])
     assert_int_equal(d[2], oracle_bfs("rmat12", 9))
+    assert_int_equal(d[0], oracle_bfs("rmat12", 5))
 
 
 @pytest.mark.parametrize("name", ["rmat12", "rmat14", "star5000", "cliques", "isolated7", "single", "fullgrid34",
