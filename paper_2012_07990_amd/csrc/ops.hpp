@@ -125,7 +125,6 @@ struct Workspace {
     DevBuf<float> pr_contrib[2];  // PageRank
     DevBuf<double> pr_acc, pr_head, pr_tail;
     DevBuf<double> pr_partial, pr_dangling;
-    DevBuf<unsigned> pr_done;
     DevBuf<unsigned long long> ms_sigma;  // multi-source BC path counts (vertex-major)
     DevBuf<unsigned> barrier;             // grid barrier state for fused kernels
     HostPinned<int32_t> h_i32;            // pinned readback slots

@@ -40,8 +40,7 @@ struct PrArgs {
     float damping;
     const double *D_in;     // dangling mass of the input round
     double *D_out;
-    double *partials;       // per-block dangling partial sums
-    unsigned *done;         // last-block ticket
+    double *partials;       // per-block dangling partial sums (reduced by k_pr_dangling)
     int dangling;           // 0: drop the dangling mass
     double *acc;            // STRICT / PUSH accumulators (reset after read)
 };
@@ -58,11 +57,11 @@ __device__ __forceinline__ void pr_apply(const PrArgs &a, int v, double base, do
     if (deg == 0) dl += (double)nv;
 }
 
-// Block sum of the dangling partials, then the last block to finish reduces
-// all block partials (fixed order) into D_out.
+// Block sum of the dangling ranks into the block's partial; k_pr_dangling
+// reduces the partials after the kernel (a kernel boundary orders them, with
+// no per-workgroup agent-scope fence and ticket).
 __device__ void pr_finish(const PrArgs &a, double dl) {
     __shared__ double s_w[kBlock / kWave];
-    __shared__ bool s_last;
     dl = wave_sum(dl);
     if (lane_id() == 0) s_w[threadIdx.x / kWave] = dl;
     __syncthreads();
@@ -70,25 +69,21 @@ __device__ void pr_finish(const PrArgs &a, double dl) {
         double t = 0;
         for (int w = 0; w < kBlock / kWave; w++) t += s_w[w];
         a.partials[blockIdx.x] = t;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const unsigned ticket = __hip_atomic_fetch_add(a.done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = ticket == gridDim.x - 1;
     }
-    __syncthreads();
-    if (!s_last) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// D_out = the sum of `count` block partials, in a fixed order
+__global__ __launch_bounds__(kBlock) void k_pr_dangling(const double *partials, int count, double *D_out) {
+    __shared__ double s_w[kBlock / kWave];
     double t = 0;
-    for (unsigned i = threadIdx.x; i < gridDim.x; i += kBlock)
-        t += __hip_atomic_load(&a.partials[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int i = threadIdx.x; i < count; i += kBlock) t += partials[i];
     t = wave_sum(t);
-    __syncthreads();
     if (lane_id() == 0) s_w[threadIdx.x / kWave] = t;
     __syncthreads();
     if (threadIdx.x == 0) {
         double s = 0;
         for (int w = 0; w < kBlock / kWave; w++) s += s_w[w];
-        *a.D_out = s;
-        *a.done = 0;
+        *D_out = s;
     }
 }
 
@@ -458,7 +453,6 @@ void pr_run(Graph &G, const gg_schedule &sch, float damping, int iters, uint32_t
     ws->pr_contrib[1].ensure(n);
     ws->pr_partial.ensure(apply_blocks + 1);
     ws->pr_dangling.ensure(2);
-    ws->pr_done.ensure(1);
     const bool strict = !push && lb == GG_LB_STRICT;
     PullBlocked *pb = nullptr;
     if (strict || push) ws->pr_acc.ensure(n);
@@ -469,7 +463,6 @@ void pr_run(Graph &G, const gg_schedule &sch, float damping, int iters, uint32_t
         ws->pr_head.ensure((size_t)maxc);
         ws->pr_tail.ensure((size_t)maxc);
     }
-    fill_i32(c, reinterpret_cast<int32_t *>(ws->pr_done.p), 1, 0);
     KernelTimer kt;
     kt.on = st && (st->flags & GG_STATS_TIME_KERNELS);
     kt.s = c.s;
@@ -482,7 +475,6 @@ void pr_run(Graph &G, const gg_schedule &sch, float damping, int iters, uint32_t
     a.damping = damping;
     a.dangling = (flags & GG_PR_NO_DANGLING) ? 0 : 1;
     a.partials = ws->pr_partial.p;
-    a.done = ws->pr_done.p;
     a.acc = (strict || push) ? ws->pr_acc.p : nullptr;
     // round 0
     a.contrib_out = ws->pr_contrib[0].p;
@@ -490,7 +482,9 @@ void pr_run(Graph &G, const gg_schedule &sch, float damping, int iters, uint32_t
     a.D_out = ws->pr_dangling.p + 0;
     hipLaunchKernelGGL(k_pr_init, dim3(nblk), dim3(kBlock), 0, c.s, a);
     GG_CHECK_LAUNCH();
-    c.launches++;
+    hipLaunchKernelGGL(k_pr_dangling, dim3(1), dim3(kBlock), 0, c.s, a.partials, (int)nblk, a.D_out);
+    GG_CHECK_LAUNCH();
+    c.launches += 2;
     for (int t = 0; t < iters; t++) {
         a.contrib_in = ws->pr_contrib[t & 1].p;
         a.contrib_out = ws->pr_contrib[(t + 1) & 1].p;
@@ -551,7 +545,10 @@ void pr_run(Graph &G, const gg_schedule &sch, float damping, int iters, uint32_t
             kt.end();
         }
         GG_CHECK_LAUNCH();
-        c.launches++;
+        const unsigned nparts = (!push && !strict && lb == GG_LB_WM) ? nblk_wm : nblk;
+        hipLaunchKernelGGL(k_pr_dangling, dim3(1), dim3(kBlock), 0, c.s, a.partials, (int)nparts, a.D_out);
+        GG_CHECK_LAUNCH();
+        c.launches += 2;
     }
     GG_HIP(hipEventRecord(e1, c.s));
     GG_HIP(hipEventSynchronize(e1));
