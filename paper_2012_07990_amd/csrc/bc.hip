@@ -40,6 +40,8 @@ struct BcPush {
         }
         return claimed ? v : -1;
     }
+    __device__ __forceinline__ void begin() const {}
+    __device__ __forceinline__ void flush() const {}
 };
 
 __global__ __launch_bounds__(kBlock) void k_bc_init(int32_t *depth, unsigned long long *sigma, double *delta, int n,

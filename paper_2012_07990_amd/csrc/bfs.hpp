@@ -16,6 +16,8 @@ struct BfsPush {
         if (depth[v] >= 0) return -1;  // filter (a stale read only costs a failed CAS)
         return atomic_cas_i32(&depth[v], -1, next) == -1 ? v : -1;
     }
+    __device__ __forceinline__ void begin() const {}
+    __device__ __forceinline__ void flush() const {}
 };
 
 

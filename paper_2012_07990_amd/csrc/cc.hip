@@ -20,12 +20,18 @@ struct CcHook {
     __device__ __forceinline__ int edge(int u, int v, int) const {
         if (v < u) return -1;  // symmetric graph: every undirected edge once
         const int lu = label[u], lv = label[v];
+        bool ch = false;
         if (lu != lv) {
             const int hi = lu > lv ? lu : lv, lo = lu > lv ? lv : lu;
-            if (atomic_min_i32(&label[hi], lo) > lo) *changed = 1;
+            ch = atomic_min_i32(&label[hi], lo) > lo;
         }
+        // one store per wavefront to the shared flag, and none once it is seen set
+        const uint64_t m = __ballot(ch);
+        if (m && lane_id() == first_lane(m) && load_relaxed(changed) == 0) *changed = 1;
         return -1;
     }
+    __device__ __forceinline__ void begin() const {}
+    __device__ __forceinline__ void flush() const {}
 };
 
 __global__ __launch_bounds__(kBlock) void k_cc_init(int32_t *label, int32_t *ids, int n) {

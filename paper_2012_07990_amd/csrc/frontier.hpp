@@ -65,6 +65,50 @@ __device__ __forceinline__ void wave_append(int32_t *q, int32_t *count, int32_t 
     }
 }
 
+// Appends staged per workgroup: lanes reserve LDS slots (one LDS atomic per
+// wavefront) and the workgroup publishes them with one global atomic when it
+// flushes. Every workgroup of a traversal appends to the same queue, so
+// per-wavefront global atomics serialise on one address (measured: halving
+// the batched SSSP loop's time); slots past the LDS capacity fall back to
+// the per-wavefront global append.
+constexpr int kStage = 2048;
+
+struct Staged {
+    int32_t *sq;     // LDS slots
+    int *sc;         // LDS count (may pass kStage: the excess went global)
+    int32_t *q;      // global queue
+    int32_t *count;  // its global count
+};
+
+__device__ __forceinline__ void stage_append(const Staged &st, int32_t cap, int32_t *overflow, bool want, int v) {
+    const uint64_t mask = __ballot(want);
+    if (mask == 0) return;
+    const int leader = first_lane(mask);
+    int base = 0;
+    if (lane_id() == leader) base = __hip_atomic_fetch_add(st.sc, __popcll(mask), __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_WORKGROUP);
+    base = wave_bcast(base, leader);
+    const int pos = base + lanes_below(mask);
+    if (want && pos < kStage) st.sq[pos] = v;
+    wave_append(st.q, st.count, cap, overflow, want && pos >= kStage, v);
+}
+
+// every lane of the workgroup calls this; leaves the LDS count at zero
+__device__ __forceinline__ void stage_flush(const Staged &st, int32_t cap, int32_t *overflow, int *s_base) {
+    __syncthreads();
+    const int cnt = min(*st.sc, kStage);
+    if (threadIdx.x == 0) *s_base = cnt > 0 ? atomic_add_i32(st.count, cnt) : 0;
+    __syncthreads();
+    const int base = *s_base;
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        if (base + i < cap) st.q[base + i] = st.sq[i];
+        else *overflow = 1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *st.sc = 0;
+    __syncthreads();
+}
+
 // Output-frontier sink used inside edge loops (FUSED creation calls the
 // wave-aggregated append; the unfused forms mark a dense map).
 template <int CREATE, int DEDUP>
@@ -77,6 +121,29 @@ __device__ __forceinline__ void emit(const OutFrontier &o, bool want, int v) {
     } else {
         if (want) atomic_or_u64(&o.bitmap[v >> 6], 1ull << (v & 63));
     }
+}
+
+// Workgroup-staged form of emit (FUSED creation stages in LDS; the dense-map
+// forms need no queue). `s` is the workgroup's LDS stage; the caller flushes
+// it at workgroup-uniform points.
+struct StageLDS {
+    int32_t q[kStage];
+    int c, base;
+};
+
+template <int CREATE, int DEDUP>
+__device__ __forceinline__ void emit_staged(const OutFrontier &o, StageLDS &s, bool want, int v) {
+    if constexpr (CREATE == kCreateFused) {
+        if (want) want = dedup_first<DEDUP>(o, v);
+        stage_append(Staged{s.q, &s.c, o.q, o.count}, o.cap, o.overflow, want, v);
+    } else {
+        emit<CREATE, DEDUP>(o, want, v);
+    }
+}
+
+template <int CREATE>
+__device__ __forceinline__ void emit_flush(const OutFrontier &o, StageLDS &s) {
+    if constexpr (CREATE == kCreateFused) stage_flush(Staged{s.q, &s.c, o.q, o.count}, o.cap, o.overflow, &s.base);
 }
 
 // ---- dense-map membership ----------------------------------------------------------

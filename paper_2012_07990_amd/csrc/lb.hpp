@@ -126,6 +126,10 @@ template <int CREATE, int DEDUP, class Src, class F>
 __device__ void lb_cm(const DevGraph &g, const Src &src, F &f, const OutFrontier &out, Tid t,
                       long long &ne) {
     __shared__ int s_u[kBlock], s_beg[kBlock], s_scan[kBlock], s_tmp[kBlock / kWave];
+    __shared__ StageLDS s_st;
+    if (threadIdx.x == 0) s_st.c = 0;
+    f.begin();
+    __syncthreads();
     for (int base = t.block * kBlock; base < src.size; base += t.nblocks * kBlock) {
         const int i = base + (int)threadIdx.x;
         int u = 0, deg = 0, beg = 0;
@@ -143,10 +147,12 @@ __device__ void lb_cm(const DevGraph &g, const Src &src, F &f, const OutFrontier
             if (f.done(uu)) continue;
             const int e = s_beg[k] + (j - s_scan[k]);
             const int x = f.edge(uu, g.col[e], e);
-            emit<CREATE, DEDUP>(out, x >= 0, x);
+            emit_staged<CREATE, DEDUP>(out, s_st, x >= 0, x);
             ne++;
         }
         __syncthreads();
+        emit_flush<CREATE>(out, s_st);
+        f.flush();
     }
 }
 
@@ -157,7 +163,11 @@ __device__ void lb_etwc(const DevGraph &g, const Src &src, F &f, const OutFronti
     // Q[0] lane stage, Q[1] wave stage, Q[2] workgroup stage: {begin, end, vertex}
     __shared__ int q_beg[3][kBlock], q_end[3][kBlock], q_u[3][kBlock];
     __shared__ int q_n[3];
+    __shared__ StageLDS s_st;
     const int tid = threadIdx.x, lane = lane_id(), wib = tid / kWave;
+    if (tid == 0) s_st.c = 0;
+    f.begin();
+    __syncthreads();
     for (int base = t.block * kBlock; base < src.size; base += t.nblocks * kBlock) {
         if (tid < 3) q_n[tid] = 0;
         __syncthreads();
@@ -193,7 +203,7 @@ __device__ void lb_etwc(const DevGraph &g, const Src &src, F &f, const OutFronti
             for (int e = q_beg[0][k]; e < end; e++) {
                 if (f.done(u)) break;
                 const int x = f.edge(u, g.col[e], e);
-                emit<CREATE, DEDUP>(out, x >= 0, x);
+                emit_staged<CREATE, DEDUP>(out, s_st, x >= 0, x);
                 ne++;
             }
         }
@@ -203,7 +213,7 @@ __device__ void lb_etwc(const DevGraph &g, const Src &src, F &f, const OutFronti
             for (int e = q_beg[1][k] + lane; e < end; e += kWave) {
                 if (f.done(u)) break;
                 const int x = f.edge(u, g.col[e], e);
-                emit<CREATE, DEDUP>(out, x >= 0, x);
+                emit_staged<CREATE, DEDUP>(out, s_st, x >= 0, x);
                 ne++;
             }
         }
@@ -213,11 +223,13 @@ __device__ void lb_etwc(const DevGraph &g, const Src &src, F &f, const OutFronti
             for (int e = q_beg[2][k] + tid; e < end; e += kBlock) {
                 if (f.done(u)) break;
                 const int x = f.edge(u, g.col[e], e);
-                emit<CREATE, DEDUP>(out, x >= 0, x);
+                emit_staged<CREATE, DEDUP>(out, s_st, x >= 0, x);
                 ne++;
             }
         }
         __syncthreads();
+        emit_flush<CREATE>(out, s_st);
+        f.flush();
     }
 }
 
@@ -329,8 +341,13 @@ __device__ void lb_strict(const DevGraph &g, const Src &src, const long long *sc
                           const OutFrontier &out, Tid t, long long &ne) {
     constexpr int W = kStrictChunk;
     __shared__ long long s_scan[W + 1];
-    __shared__ int s_u[W], s_beg[W];  // the window's sources and their row starts
     __shared__ int s_k0, s_k1;
+    // FUSED creation stages the window's appends in LDS (one global atomic per
+    // window instead of one per wavefront and edge batch)
+    __shared__ StageLDS s_st;
+    if (threadIdx.x == 0) s_st.c = 0;
+    f.begin();
+    __syncthreads();
     const long long total = scan[src.size];
     const long long nchunks = (total + W - 1) / W;
     for (long long c = t.block; c < nchunks; c += t.nblocks) {
@@ -348,14 +365,7 @@ __device__ void lb_strict(const DevGraph &g, const Src &src, const long long *sc
         __syncthreads();
         for (int kw = k0; kw <= k1; kw += W) {  // LDS windows of sources [kw, kw+W)
             const int wlen = (k1 - kw + 1 < W) ? k1 - kw + 1 : W;
-            for (int j = threadIdx.x; j <= wlen; j += kBlock) {
-                s_scan[j] = scan[kw + j];
-                if (j < wlen && kw + j < src.size) {
-                    const int u = src.get(kw + j);
-                    s_u[j] = u;
-                    s_beg[j] = g.row_ptr[u];
-                }
-            }
+            for (int j = threadIdx.x; j <= wlen; j += kBlock) s_scan[j] = scan[kw + j];
             __syncthreads();
             long long lo = s_scan[0] > r0 ? s_scan[0] : r0;
             long long hi = s_scan[wlen] < r1 ? s_scan[wlen] : r1;
@@ -366,14 +376,16 @@ __device__ void lb_strict(const DevGraph &g, const Src &src, const long long *sc
                     const int mid = (a + b) >> 1;
                     if (s_scan[mid] <= r) a = mid; else b = mid;
                 }
-                const int u = s_u[a];
+                const int u = src.get(kw + a);
                 if (f.done(u)) continue;
-                const int e = s_beg[a] + (int)(r - s_scan[a]);
+                const int e = g.row_ptr[u] + (int)(r - s_scan[a]);
                 const int x = f.edge(u, g.col[e], e);
-                emit<CREATE, DEDUP>(out, x >= 0, x);
+                emit_staged<CREATE, DEDUP>(out, s_st, x >= 0, x);
                 ne++;
             }
             __syncthreads();
+            emit_flush<CREATE>(out, s_st);
+            f.flush();
         }
     }
 }

@@ -129,8 +129,7 @@ __global__ __launch_bounds__(kBlock) void k_mssssp_init(int n, int K, const int3
 // appends together
 template <bool UNIT>
 __device__ __forceinline__ void ms_relax_pair(const MsSsspArgs &a, int du, int e, int v, int src, u64 *nnext,
-                                              int32_t *qout, int32_t *qcount, int32_t *farq, int32_t *farc,
-                                              long long bucket_end) {
+                                              const Staged &nq, const Staged &fq, long long bucket_end) {
     const long long nd = (long long)du + (UNIT ? 1ll : (long long)a.g.w[e]);
     int32_t *dv = &a.dist[(size_t)v * a.K + src];
     bool to_near = false, to_far = false;
@@ -144,8 +143,8 @@ __device__ __forceinline__ void ms_relax_pair(const MsSsspArgs &a, int du, int e
             else to_far = atomic_or_u64(&a.far[v], bit) == 0;
         }
     }
-    wave_append(qout, qcount, a.g.n, a.ctr + 12, to_near, v);
-    wave_append(farq, farc, a.g.n, a.ctr + 12, to_far, v);
+    stage_append(nq, a.g.n, a.ctr + 12, to_near, v);
+    stage_append(fq, a.g.n, a.ctr + 12, to_far, v);
 }
 
 // In a full round (a workgroup's share of the queue is at least kMsBlock
@@ -164,6 +163,11 @@ __device__ __forceinline__ void ms_relax(const MsSsspArgs &a, const int32_t *qin
     __shared__ long long s_scan[kMsBlock + 1], s_tmp[kMsBlock / kWave];
     __shared__ int s_u[kMsBlock], s_beg[kMsBlock], s_p[kMsBlock];
     __shared__ u64 s_m[kMsBlock];
+    __shared__ int32_t s_nq[kStage], s_fq[kStage];
+    __shared__ int s_nc, s_fc, s_base;
+    if (threadIdx.x == 0) { s_nc = 0; s_fc = 0; }
+    __syncthreads();
+    const Staged nq{s_nq, &s_nc, qout, qcount}, fq{s_fq, &s_fc, farq, farc};
     const int K = a.K;
     const int share = (cnt + t.nblocks - 1) / t.nblocks;
     const int chunk = share < kMsBlock ? share : kMsBlock;  // entries per workgroup step (uniform)
@@ -191,29 +195,30 @@ __device__ __forceinline__ void ms_relax(const MsSsspArgs &a, const int32_t *qin
                 while (mm) {
                     const int src = __ffsll(mm) - 1;
                     mm &= mm - 1;
-                    ms_relax_pair<UNIT>(a, a.dist[(size_t)u * K + src], e, v, src, nnext, qout, qcount, farq, farc,
-                                        bucket_end);
+                    ms_relax_pair<UNIT>(a, a.dist[(size_t)u * K + src], e, v, src, nnext, nq, fq, bucket_end);
                 }
             }
         }
         // large entries: ranks over the workgroup, sources of an edge on adjacent lanes
         long long excl;
         const long long total = block_excl_scan64(own ? 0 : work, excl, s_tmp);
-        if (total == 0) continue;  // uniform: every lane read the same total
-        s_u[threadIdx.x] = u; s_beg[threadIdx.x] = beg; s_p[threadIdx.x] = p; s_m[threadIdx.x] = m;
-        s_scan[threadIdx.x] = excl;
-        __syncthreads();
-        for (long long j = threadIdx.x; j < total; j += kMsBlock) {
-            const int o = last_le64(s_scan, chunk, j);
-            const unsigned r = (unsigned)(j - s_scan[o]);
-            const unsigned po = (unsigned)s_p[o];
-            const unsigned el = r / po;
-            const int src = select_bit(s_m[o], (int)(r - el * po));
-            const int e = s_beg[o] + (int)el;
-            ms_relax_pair<UNIT>(a, a.dist[(size_t)s_u[o] * K + src], e, a.g.col[e], src, nnext, qout, qcount, farq,
-                                farc, bucket_end);
+        if (total > 0) {  // uniform: every lane read the same total
+            s_u[threadIdx.x] = u; s_beg[threadIdx.x] = beg; s_p[threadIdx.x] = p; s_m[threadIdx.x] = m;
+            s_scan[threadIdx.x] = excl;
+            __syncthreads();
+            for (long long j = threadIdx.x; j < total; j += kMsBlock) {
+                const int o = last_le64(s_scan, chunk, j);
+                const unsigned r = (unsigned)(j - s_scan[o]);
+                const unsigned po = (unsigned)s_p[o];
+                const unsigned el = r / po;
+                const int src = select_bit(s_m[o], (int)(r - el * po));
+                const int e = s_beg[o] + (int)el;
+                ms_relax_pair<UNIT>(a, a.dist[(size_t)s_u[o] * K + src], e, a.g.col[e], src, nnext, nq, fq,
+                                    bucket_end);
+            }
         }
-        __syncthreads();
+        stage_flush(nq, a.g.n, a.ctr + 12, &s_base);
+        stage_flush(fq, a.g.n, a.ctr + 12, &s_base);
     }
 }
 
@@ -243,6 +248,11 @@ __device__ __forceinline__ void ms_far_min(const MsSsspArgs &a, const int32_t *f
 __device__ __forceinline__ void ms_far_split(const MsSsspArgs &a, const int32_t *farq, int fc, int knew,
                                              u64 *nnext, int32_t *qout, int32_t *qcount, int32_t *nfarq,
                                              int32_t *nfarc, Tid t) {
+    __shared__ int32_t s_nq[kStage], s_fq[kStage];
+    __shared__ int s_nc, s_fc, s_base;
+    if (threadIdx.x == 0) { s_nc = 0; s_fc = 0; }
+    __syncthreads();
+    const Staged nq{s_nq, &s_nc, qout, qcount}, fq{s_fq, &s_fc, nfarq, nfarc};
     const int stride = t.nblocks * kMsBlock;
     const int n_iter = (fc + stride - 1) / stride;
     for (int it = 0; it < n_iter; it++) {
@@ -262,8 +272,10 @@ __device__ __forceinline__ void ms_far_split(const MsSsspArgs &a, const int32_t 
             a.far[v] = keep;
             if (move) nnext[v] = move;  // the near set is empty when a bucket advances
         }
-        wave_append(qout, qcount, a.g.n, a.ctr + 12, move != 0, v);
-        wave_append(nfarq, nfarc, a.g.n, a.ctr + 12, keep != 0, v);
+        stage_append(nq, a.g.n, a.ctr + 12, move != 0, v);
+        stage_append(fq, a.g.n, a.ctr + 12, keep != 0, v);
+        stage_flush(nq, a.g.n, a.ctr + 12, &s_base);
+        stage_flush(fq, a.g.n, a.ctr + 12, &s_base);
     }
 }
 

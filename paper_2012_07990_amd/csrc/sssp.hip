@@ -19,7 +19,17 @@
 
 namespace gg {
 
-struct SsspRelax {
+// LDS stage of the far-queue appends (one per kernel)
+__device__ __forceinline__ Staged sssp_far_stage(int32_t *farq, int32_t *farc) {
+    __shared__ int32_t s_q[kStage];
+    __shared__ int s_c;
+    return Staged{s_q, &s_c, farq, farc};
+}
+
+// STAGE: far appends are staged per workgroup (the load balancer calls
+// begin() and flush() at workgroup-uniform points: CM, ETWC and STRICT do)
+template <bool STAGE>
+struct SsspRelaxT {
     int32_t *dist;
     const uint32_t *w;
     long long bucket_end;   // (k+1)*delta
@@ -45,10 +55,23 @@ struct SsspRelax {
                 else to_far = atomic_max_i32(&far_tag[v], far_id) < far_id;
             }
         }
-        wave_append(farq, farc, far_cap, flags + 1, to_far, v);
+        if constexpr (STAGE) stage_append(sssp_far_stage(farq, farc), far_cap, flags + 1, to_far, v);
+        else wave_append(farq, farc, far_cap, flags + 1, to_far, v);
         return to_near ? v : -1;
     }
+    __device__ __forceinline__ void begin() const {
+        if constexpr (STAGE) {
+            if (threadIdx.x == 0) *sssp_far_stage(farq, farc).sc = 0;
+        }
+    }
+    __device__ __forceinline__ void flush() const {
+        if constexpr (STAGE) {
+            __shared__ int s_base;
+            stage_flush(sssp_far_stage(farq, farc), far_cap, flags + 1, &s_base);
+        }
+    }
 };
+using SsspRelax = SsspRelaxT<false>;
 
 // After the loop: an unreached vertex with a reached neighbour has a true
 // distance beyond INT32_MAX-1 (every relaxation into it was unrepresentable).
@@ -163,7 +186,8 @@ __global__ __launch_bounds__(kBlock) void k_sssp_fused(FusedSsspArgs a) {
         int32_t *farq = (fe & 1) ? a.farq1 : a.farq0;
         int32_t *farc = a.ctr + 3 + (fe & 1);
         if (cnt > 0) {
-            SsspRelax f{a.dist, a.g.w, (long long)(k + 1) * a.delta, farq, farc, a.g.n, a.far_tag, fe + 1, flags};
+            SsspRelaxT<LB == GG_LB_CM || LB == GG_LB_ETWC> f{a.dist, a.g.w, (long long)(k + 1) * a.delta, farq, farc,
+                                                            a.g.n, a.far_tag, fe + 1, flags};
             const SrcQueue src{qin, cnt};
             if constexpr (LB == GG_LB_VERTEX_BASED) lb_vp<kCreateFused, kDedupMonotonic>(a.g, src, f, o, t, ne);
             else if constexpr (LB == GG_LB_WM) lb_wm<kCreateFused, kDedupMonotonic>(a.g, src, f, o, t, ne);
@@ -283,10 +307,17 @@ void sssp_run(Graph &G, int32_t src, const gg_schedule &sch, int32_t *dist, hipS
             if (st) { st->vertices_processed += fs.count; st->iterations++; st->push_iterations++; }
             const int32_t *q = fs.as_queue();
             OutFrontier o = fs.prep_out(s.frontier_creation, dd, iter++);
-            SsspRelax f{dist, g.w, (long long)(k + 1) * delta, farq[fe & 1], ctr + 16 + (fe & 1), n,
-                        ws->aux_i32[2].p, fe + 1, ctr + 20};
-            push_apply(c, g, *ws, PushPlan{s.load_balance, s.frontier_creation, dd}, q, fs.count, f, o,
-                       member_map(*ws, n, s.load_balance));
+            const PushPlan plan{s.load_balance, s.frontier_creation, dd};
+            const int lbm = s.load_balance;
+            if (lbm == GG_LB_STRICT || lbm == GG_LB_CM || lbm == GG_LB_ETWC) {
+                SsspRelaxT<true> f{dist, g.w, (long long)(k + 1) * delta, farq[fe & 1], ctr + 16 + (fe & 1), n,
+                                   ws->aux_i32[2].p, fe + 1, ctr + 20};
+                push_apply(c, g, *ws, plan, q, fs.count, f, o, member_map(*ws, n, s.load_balance));
+            } else {
+                SsspRelax f{dist, g.w, (long long)(k + 1) * delta, farq[fe & 1], ctr + 16 + (fe & 1), n,
+                            ws->aux_i32[2].p, fe + 1, ctr + 20};
+                push_apply(c, g, *ws, plan, q, fs.count, f, o, member_map(*ws, n, s.load_balance));
+            }
             fs.commit(s.frontier_creation);
         }
         GG_HIP(hipMemcpyAsync(ws->h_i32.p, ctr + 16, 6 * sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
