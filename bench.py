@@ -80,7 +80,7 @@ def schedules(gg):
     bfs = gg.schedule_preset(gg.ALGO_BFS, gg.PRESET_POWERLAW)
     bfs.s1.load_balance = gg.LB_STRICT
     bfs.threshold = 0.01
-    sssp = gg.make_schedule(lb="strict", delta=64)
+    sssp = gg.make_schedule(lb="strict", delta=4096)
     cc = gg.make_schedule(lb="etwc")
     pr = gg.make_schedule(lb="strict", direction=gg.PULL, edge_blocking=True, blocking_size=PR_SEGMENT)
     bc = gg.schedule_preset(gg.ALGO_BC, gg.PRESET_POWERLAW)
@@ -116,6 +116,8 @@ def sweep_schedules(gg):
         for lb in ["wm", "etwc", "cm", "strict", "twc"]:
             out["sssp"]["%s-d%d" % (lb, d)] = gg.make_schedule(lb=lb, delta=d)
         out["sssp"]["fused-etwc-d%d" % d] = gg.make_schedule(lb="etwc", delta=d, fusion=True)
+    for d in [2048, 4096, 16384, 1 << 20]:
+        out["sssp"]["strict-d%d" % d] = gg.make_schedule(lb="strict", delta=d)
     out["sssp"]["strict-d64-nodedup"] = gg.make_schedule(lb="strict", delta=64, dedup=False)
     out["sssp"]["strict-d64-bitmapdedup"] = gg.make_schedule(lb="strict", delta=64, dedup_type=gg.DEDUP_BITMAP)
     for lb in ["vp", "wm", "etwc", "strict"]:
@@ -412,23 +414,25 @@ def batched_section(gg, graphgen, torch):
            "ms_batched": round(t_multi * 1e3, 3), "ms_single_calls": round(t_single * 1e3, 3),
            "speedup": round(t_single / t_multi, 2), "gteps_batched": round(edges / t_multi / 1e9, 2),
            "queries_per_s": round(80 / t_multi, 1), "bit_identical": ok}
-    # 64 SSSP sources: on R-MAT 20 (delta 64) and on the 2048^2 grid (delta 512),
-    # against single calls (on the grid 4 single calls stand for the 64)
+    # 64 SSSP sources: on R-MAT 20 and on the 2048^2 grid, each form with its
+    # fastest delta (batched 64 / single STRICT 4096 on R-MAT; 512 for both on
+    # the grid), against single calls (on the grid 4 single calls stand for the 64)
     out["sssp"] = []
-    for name, Gx, srcs, single_s, nsingle in [
-            ("rmat20", G, bfs_src, gg.make_schedule(lb="etwc", delta=64), 64),
-            ("grid2048", None, None, gg.make_schedule(lb="cm", delta=512, fusion=True), 4)]:
+    for name, Gx, srcs, single_s, ms_delta, nsingle in [
+            ("rmat20", G, bfs_src, gg.make_schedule(lb="strict", delta=4096), 64, 64),
+            ("grid2048", None, None, gg.make_schedule(lb="cm", delta=512, fusion=True), 512, 4)]:
         if Gx is None:
             gh = graphgen.grid(2048)
             Gx = gg.Graph.from_graphgen(gh)
             srcs = graphgen.sample_sources(gh, 64, 7)
-        ms_s = gg.make_schedule(delta=single_s.s1.delta)
+        ms_s = gg.make_schedule(delta=ms_delta)
         st = gg.Stats()
         dm = Gx.sssp_multi(srcs, ms_s, stats=st)
         ok_s = all(bool(torch.equal(dm[i], Gx.sssp(int(srcs[i]), single_s))) for i in range(0, 64, 21))
         t_m = timed(lambda: Gx.sssp_multi(srcs, ms_s), reps=1 if name.startswith("grid") else 3)
         t_1 = timed(lambda: [Gx.sssp(int(x), single_s) for x in srcs[:nsingle]], reps=1) * 64 / nsingle
-        rec = {"graph": name, "k": 64, "delta": int(single_s.s1.delta), "ms_batched": round(t_m * 1e3, 3),
+        rec = {"graph": name, "k": 64, "delta_batched": ms_delta, "delta_single": int(single_s.s1.delta),
+               "ms_batched": round(t_m * 1e3, 3),
                "ms_single_calls": round(t_1 * 1e3, 3), "single_calls_timed": nsingle,
                "speedup": round(t_1 / t_m, 2), "rounds": st.iterations, "buckets": st.buckets,
                "queries_per_s": round(64 / t_m, 1), "bit_identical": ok_s}

@@ -26,8 +26,11 @@ struct BcPush {
     int32_t *ovf;
     __device__ __forceinline__ bool active(int) const { return true; }
     __device__ __forceinline__ bool done(int) const { return false; }
-    __device__ __forceinline__ int edge(int u, int v, int) const {
-        int d = depth[v];
+    using Pre = int;
+    __device__ __forceinline__ Pre load(int, int v, int) const { return depth[v]; }
+    __device__ __forceinline__ int edge(int u, int v, int e) const { return apply(u, v, e, load(u, v, e)); }
+    __device__ __forceinline__ int apply(int u, int v, int, Pre dv) const {
+        int d = dv;
         bool claimed = false;
         if (d < 0) {
             d = atomic_cas_i32(&depth[v], -1, next);

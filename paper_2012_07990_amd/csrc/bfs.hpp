@@ -12,10 +12,15 @@ struct BfsPush {
     int next;
     __device__ __forceinline__ bool active(int) const { return true; }
     __device__ __forceinline__ bool done(int) const { return false; }
-    __device__ __forceinline__ int edge(int, int v, int) const {
-        if (depth[v] >= 0) return -1;  // filter (a stale read only costs a failed CAS)
+    // load() issues the edge's reads (no side effects), apply() its updates;
+    // load balancers batch the loads of several edges before applying them
+    using Pre = int;
+    __device__ __forceinline__ Pre load(int, int v, int) const { return depth[v]; }
+    __device__ __forceinline__ int apply(int, int v, int, Pre dv) const {
+        if (dv >= 0) return -1;  // filter (a stale read only costs a failed CAS)
         return atomic_cas_i32(&depth[v], -1, next) == -1 ? v : -1;
     }
+    __device__ __forceinline__ int edge(int u, int v, int e) const { return apply(u, v, e, load(u, v, e)); }
     __device__ __forceinline__ void begin() const {}
     __device__ __forceinline__ void flush() const {}
 };

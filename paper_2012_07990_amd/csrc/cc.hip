@@ -17,13 +17,25 @@ struct CcHook {
     int32_t *changed;
     __device__ __forceinline__ bool active(int) const { return true; }
     __device__ __forceinline__ bool done(int) const { return false; }
-    __device__ __forceinline__ int edge(int u, int v, int) const {
+    // the last hook this lane made: label[m_hi] <= m_lo holds from then on
+    // (labels only decrease), so a hook of m_hi to a value >= m_lo is a no-op
+    // and is skipped -- the lanes sharing a hub's edges would otherwise all
+    // hit the hub's label with atomics
+    mutable int m_hi = -1, m_lo = 0;
+    struct Pre { int lu, lv; };
+    __device__ __forceinline__ Pre load(int u, int v, int) const { return Pre{label[u], v < u ? 0 : label[v]}; }
+    __device__ __forceinline__ int edge(int u, int v, int e) const { return apply(u, v, e, load(u, v, e)); }
+    __device__ __forceinline__ int apply(int u, int v, int, const Pre &p) const {
         if (v < u) return -1;  // symmetric graph: every undirected edge once
-        const int lu = label[u], lv = label[v];
+        const int lu = p.lu, lv = p.lv;  // stale labels only delay a hook to a later round
         bool ch = false;
         if (lu != lv) {
             const int hi = lu > lv ? lu : lv, lo = lu > lv ? lv : lu;
-            ch = atomic_min_i32(&label[hi], lo) > lo;
+            if (hi != m_hi || lo < m_lo) {
+                ch = atomic_min_i32(&label[hi], lo) > lo;
+                m_hi = hi;
+                m_lo = lo;
+            }
         }
         // one store per wavefront to the shared flag, and none once it is seen set
         const uint64_t m = __ballot(ch);

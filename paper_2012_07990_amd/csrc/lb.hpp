@@ -32,6 +32,11 @@
 
 namespace gg {
 
+// Edges a lane loads before applying them (load-balancer loops that issue
+// each edge's column and functor reads for several edges at once, so their
+// latencies overlap instead of adding up)
+constexpr int kEdgeBatch = 4;
+
 struct Tid {  // position of this lane in the (possibly persistent) grid
     int block, nblocks;
     __device__ static Tid here() { return Tid{(int)blockIdx.x, (int)gridDim.x}; }
@@ -197,14 +202,24 @@ __device__ void lb_etwc(const DevGraph &g, const Src &src, F &f, const OutFronti
             }
         }
         __syncthreads();
-        // stage 0: one lane per entry
+        // stage 0: one lane per entry, its edges in batches of kEdgeBatch
         for (int k = tid; k < q_n[0]; k += kBlock) {
             const int u = q_u[0][k], end = q_end[0][k];
-            for (int e = q_beg[0][k]; e < end; e++) {
-                if (f.done(u)) break;
-                const int x = f.edge(u, g.col[e], e);
-                emit_staged<CREATE, DEDUP>(out, s_st, x >= 0, x);
-                ne++;
+            for (int e0 = q_beg[0][k]; e0 < end; e0 += kEdgeBatch) {
+                int vv[kEdgeBatch];
+                typename F::Pre pp[kEdgeBatch];
+#pragma unroll
+                for (int b = 0; b < kEdgeBatch; b++) vv[b] = g.col[e0 + b < end ? e0 + b : end - 1];
+#pragma unroll
+                for (int b = 0; b < kEdgeBatch; b++) pp[b] = f.load(u, vv[b], e0 + b < end ? e0 + b : end - 1);
+#pragma unroll
+                for (int b = 0; b < kEdgeBatch; b++) {
+                    if (e0 + b < end && !f.done(u)) {
+                        const int x = f.apply(u, vv[b], e0 + b, pp[b]);
+                        emit_staged<CREATE, DEDUP>(out, s_st, x >= 0, x);
+                        ne++;
+                    }
+                }
             }
         }
         // stage 1: one wavefront per entry, lanes cyclic over its edges
@@ -370,18 +385,41 @@ __device__ void lb_strict(const DevGraph &g, const Src &src, const long long *sc
             long long lo = s_scan[0] > r0 ? s_scan[0] : r0;
             long long hi = s_scan[wlen] < r1 ? s_scan[wlen] : r1;
             int a = 0;  // owners only move forward as r grows
-            for (long long r = lo + threadIdx.x; r < hi; r += kBlock) {
-                int b = wlen;  // last j with s_scan[j] <= r
-                while (b - a > 1) {
-                    const int mid = (a + b) >> 1;
-                    if (s_scan[mid] <= r) a = mid; else b = mid;
+            // a lane's ranks r, r + kBlock, ... in batches of kEdgeBatch: owners
+            // from LDS, then every batch member's source, row start, column and
+            // functor reads are issued before any update (ranks past hi repeat
+            // the last valid rank and are not applied)
+            for (long long rb = lo + threadIdx.x; rb < hi; rb += (long long)kEdgeBatch * kBlock) {
+                int ab[kEdgeBatch], uu[kEdgeBatch], ee[kEdgeBatch], vv[kEdgeBatch];
+                typename F::Pre pp[kEdgeBatch];
+#pragma unroll
+                for (int k = 0; k < kEdgeBatch; k++) {
+                    long long r = rb + (long long)k * kBlock;
+                    if (r >= hi) r = hi - 1;
+                    int b = wlen;  // last j with s_scan[j] <= r
+                    while (b - a > 1) {
+                        const int mid = (a + b) >> 1;
+                        if (s_scan[mid] <= r) a = mid; else b = mid;
+                    }
+                    ab[k] = a;
+                    ee[k] = (int)(r - s_scan[a]);
                 }
-                const int u = src.get(kw + a);
-                if (f.done(u)) continue;
-                const int e = g.row_ptr[u] + (int)(r - s_scan[a]);
-                const int x = f.edge(u, g.col[e], e);
-                emit_staged<CREATE, DEDUP>(out, s_st, x >= 0, x);
-                ne++;
+#pragma unroll
+                for (int k = 0; k < kEdgeBatch; k++) uu[k] = src.get(kw + ab[k]);
+#pragma unroll
+                for (int k = 0; k < kEdgeBatch; k++) ee[k] += g.row_ptr[uu[k]];
+#pragma unroll
+                for (int k = 0; k < kEdgeBatch; k++) vv[k] = g.col[ee[k]];
+#pragma unroll
+                for (int k = 0; k < kEdgeBatch; k++) pp[k] = f.load(uu[k], vv[k], ee[k]);
+#pragma unroll
+                for (int k = 0; k < kEdgeBatch; k++) {
+                    if (rb + (long long)k * kBlock < hi && !f.done(uu[k])) {
+                        const int x = f.apply(uu[k], vv[k], ee[k], pp[k]);
+                        emit_staged<CREATE, DEDUP>(out, s_st, x >= 0, x);
+                        ne++;
+                    }
+                }
             }
             __syncthreads();
             emit_flush<CREATE>(out, s_st);

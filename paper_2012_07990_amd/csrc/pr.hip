@@ -240,10 +240,23 @@ __global__ __launch_bounds__(kBlock) void k_pr_strict_chunks(const int32_t *rp, 
     const int tid = threadIdx.x, lane = lane_id(), wib = tid / kWave;
     for (long long c = blockIdx.x; c < nchunks; c += gridDim.x) {
         const long long E0 = c * kPrChunk, E1 = (E0 + kPrChunk < m) ? E0 + kPrChunk : m;
+        // all column loads, then all gathers, without branches in between (a
+        // conditional per edge made the compiler wait for each load in turn);
+        // edges past the chunk's end re-read its last edge and are not stored
+        constexpr int kPer = kPrChunk / kBlock;
+        int cidx[kPer];
+        float cval[kPer];
 #pragma unroll
-        for (int k = 0; k < kPrChunk / kBlock; k++) {
+        for (int k = 0; k < kPer; k++) {
             const long long e = E0 + k * kBlock + tid;
-            if (e < E1) vals[e - E0] = contrib[col[e]];
+            cidx[k] = col[e < E1 ? e : E1 - 1];
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; k++) cval[k] = contrib[cidx[k]];
+#pragma unroll
+        for (int k = 0; k < kPer; k++) {
+            const long long e = E0 + k * kBlock + tid;
+            if (e < E1) vals[e - E0] = cval[k];
         }
         if (tid == 0) {
             s_r0 = chunk_rows[2 * c];

@@ -41,14 +41,19 @@ struct SsspRelaxT {
     int32_t *flags;         // [0] distance overflow, [1] far queue overflow
     __device__ __forceinline__ bool active(int) const { return true; }
     __device__ __forceinline__ bool done(int) const { return false; }
-    __device__ __forceinline__ int edge(int u, int v, int e) const {
-        const long long nd = (long long)dist[u] + (long long)w[e];
+    struct Pre { long long nd; int dv; };
+    __device__ __forceinline__ Pre load(int u, int v, int e) const {
+        return Pre{(long long)dist[u] + (long long)w[e], dist[v]};
+    }
+    __device__ __forceinline__ int edge(int u, int v, int e) const { return apply(u, v, e, load(u, v, e)); }
+    __device__ __forceinline__ int apply(int, int v, int, const Pre &p) const {
+        const long long nd = p.nd;
         bool to_near = false, to_far = false;
         if (nd > (long long)INT_MAX - 1) {
             // not representable: v is unreached so far and may end up with a
             // distance beyond INT32_MAX-1 (confirmed after the loop)
-            if (dist[v] == INT_MAX) flags[0] = 1;
-        } else if (nd < dist[v]) {
+            if (p.dv == INT_MAX) flags[0] = 1;
+        } else if (nd < p.dv) {  // a stale (larger) read only costs an atomic
             const int old = atomic_min_i32(&dist[v], (int)nd);
             if (nd < old) {
                 if (nd < bucket_end) to_near = true;
