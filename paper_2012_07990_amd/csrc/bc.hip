@@ -84,7 +84,10 @@ __global__ __launch_bounds__(kBlock) void k_bc_pull(DevGraph g, int32_t *depth, 
     __shared__ int s_any[kBlock];
     const int tid = threadIdx.x, lane = lane_id(), wib = tid / kWave;
     long long ne = 0;
+    __shared__ StageLDS s_st;  // the level's queue appends, one global atomic per flush
     auto member = [&](int u) { return REP == kRepBoolmap ? (in_bool[u] != 0) : bit_test(in_bits, u); };
+    if (tid == 0) s_st.c = 0;
+    __syncthreads();
     for (int base = blockIdx.x * kBlock; base < g.n; base += gridDim.x * kBlock) {
         if (tid < 2) q_n[tid] = 0;
         s_sum[tid] = 0;
@@ -97,14 +100,24 @@ __global__ __launch_bounds__(kBlock) void k_bc_pull(DevGraph g, int32_t *depth, 
             if (deg < kWave) {
                 unsigned long long s = 0;
                 int any = 0;
-                for (int e = beg; e < end; e++) {
-                    const int u = g.col[e];
-                    ne++;
-                    if (member(u)) {
-                        const unsigned long long su = sigma[u];
-                        if (s + su < s) *ovf = 1;
-                        s += su;
-                        any = 1;
+                for (int e0 = beg; e0 < end; e0 += kEdgeBatch) {  // loads of a batch overlap
+                    int uu[kEdgeBatch];
+                    bool in[kEdgeBatch];
+                    unsigned long long su[kEdgeBatch];
+#pragma unroll
+                    for (int b = 0; b < kEdgeBatch; b++) uu[b] = g.col[e0 + b < end ? e0 + b : end - 1];
+#pragma unroll
+                    for (int b = 0; b < kEdgeBatch; b++) in[b] = e0 + b < end && member(uu[b]);
+#pragma unroll
+                    for (int b = 0; b < kEdgeBatch; b++) su[b] = in[b] ? sigma[uu[b]] : 0ull;
+#pragma unroll
+                    for (int b = 0; b < kEdgeBatch; b++) {
+                        if (e0 + b < end) ne++;
+                        if (in[b]) {
+                            if (s + su[b] < s) *ovf = 1;
+                            s += su[b];
+                            any = 1;
+                        }
                     }
                 }
                 s_sum[tid] = s;
@@ -166,8 +179,8 @@ __global__ __launch_bounds__(kBlock) void k_bc_pull(DevGraph g, int32_t *depth, 
             depth[v] = next;
             sigma[v] = s_sum[tid];
         }
-        wave_append(out.q, out.count, out.cap, out.overflow, found, v);
-        __syncthreads();
+        emit_staged<kCreateFused, kDedupNone>(out, s_st, found, v);
+        emit_flush<kCreateFused>(out, s_st);
     }
     flush_edge_count(ne, ecount);
 }
@@ -184,6 +197,35 @@ __device__ __forceinline__ double bc_term(const DevGraph &g, int e, int dv1, dou
                                           const unsigned long long *sigma, const double *delta, double acc) {
     const int w = g.col[e];
     return depth[w] == dv1 ? bc_step(acc, sv, (double)sigma[w], delta[w]) : acc;
+}
+
+// The terms of edges e0, e0 + stride, ... below e_end, in that order, with the
+// loads of kEdgeBatch edges issued before their steps (the order of the
+// steps, and so the rounding, is the plain loop's).
+__device__ __forceinline__ double bc_terms(const DevGraph &g, int e0, int e_end, int stride, int dv1, double sv,
+                                           const int32_t *depth, const unsigned long long *sigma,
+                                           const double *delta, double acc) {
+    for (int e = e0; e < e_end; e += kEdgeBatch * stride) {
+        int ww[kEdgeBatch], dd[kEdgeBatch];
+        double sg[kEdgeBatch], dl[kEdgeBatch];
+#pragma unroll
+        for (int b = 0; b < kEdgeBatch; b++) {
+            const int eb = e + b * stride;
+            ww[b] = g.col[eb < e_end ? eb : e];
+        }
+#pragma unroll
+        for (int b = 0; b < kEdgeBatch; b++) dd[b] = depth[ww[b]];
+#pragma unroll
+        for (int b = 0; b < kEdgeBatch; b++) {
+            const bool on = e + b * stride < e_end && dd[b] == dv1;
+            sg[b] = on ? (double)sigma[ww[b]] : 1.0;
+            dl[b] = on ? delta[ww[b]] : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < kEdgeBatch; b++)
+            if (e + b * stride < e_end && dd[b] == dv1) acc = bc_step(acc, sv, sg[b], dl[b]);
+    }
+    return acc;
 }
 
 __global__ __launch_bounds__(kBlock) void k_bc_backward(DevGraph g, const int32_t *level_ids, int count,
@@ -205,9 +247,7 @@ __global__ __launch_bounds__(kBlock) void k_bc_backward(DevGraph g, const int32_
             } else if (deg < kBcWaveDeg) {
                 const int dv1 = depth[v] + 1;
                 const double sv = (double)sigma[v];
-                double acc = 0.0;
-                for (int e = g.row_ptr[v]; e < g.row_ptr[v + 1]; e++) acc = bc_term(g, e, dv1, sv, depth, sigma, delta, acc);
-                delta[v] = acc;
+                delta[v] = bc_terms(g, g.row_ptr[v], g.row_ptr[v + 1], 1, dv1, sv, depth, sigma, delta, 0.0);
             } else {
                 const int k = atomicAdd(&q_n[deg < kBcBlockDeg ? 0 : 1], 1);
                 q_v[deg < kBcBlockDeg ? 0 : 1][k] = v;
@@ -218,9 +258,7 @@ __global__ __launch_bounds__(kBlock) void k_bc_backward(DevGraph g, const int32_
             const int v = q_v[0][k];
             const int dv1 = depth[v] + 1;
             const double sv = (double)sigma[v];
-            double acc = 0.0;
-            for (int e = g.row_ptr[v] + lane; e < g.row_ptr[v + 1]; e += kWave)
-                acc = bc_term(g, e, dv1, sv, depth, sigma, delta, acc);
+            double acc = bc_terms(g, g.row_ptr[v] + lane, g.row_ptr[v + 1], kWave, dv1, sv, depth, sigma, delta, 0.0);
             acc = wave_sum(acc);
             if (lane == 0) delta[v] = acc;
         }
@@ -228,9 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_bc_backward(DevGraph g, const int32_
             const int v = q_v[1][k];
             const int dv1 = depth[v] + 1;
             const double sv = (double)sigma[v];
-            double acc = 0.0;
-            for (int e = g.row_ptr[v] + tid; e < g.row_ptr[v + 1]; e += kBlock)
-                acc = bc_term(g, e, dv1, sv, depth, sigma, delta, acc);
+            double acc = bc_terms(g, g.row_ptr[v] + tid, g.row_ptr[v + 1], kBlock, dv1, sv, depth, sigma, delta, 0.0);
             acc = wave_sum(acc);
             __syncthreads();
             if (lane == 0) s_w[wib] = acc;

@@ -23,32 +23,58 @@ template <int IN_REP, int OUT>
 __device__ __forceinline__ void bfs_pull_dev(const DevGraph &g, int32_t *depth, int next, const uint8_t *in_bool,
                                              const unsigned long long *in_bits, const OutFrontier &out, Tid t,
                                              long long &ne) {
-    const long long nr = ((long long)g.n + kWave - 1) / kWave * kWave;
+    // workgroup-uniform iterations (the appends are staged per workgroup, the
+    // unfused forms count per lane and add once per workgroup)
+    __shared__ StageLDS s_st;
+    __shared__ int s_cnt;
+    if (threadIdx.x == 0) { s_st.c = 0; s_cnt = 0; }
+    __syncthreads();
+    int found_cnt = 0;
     const long long stride = (long long)t.nblocks * kBlock;
-    for (long long v0 = (long long)t.block * kBlock + threadIdx.x; v0 < nr; v0 += stride) {
+    for (long long base = (long long)t.block * kBlock; base < g.n; base += stride) {
+        const long long v0 = base + threadIdx.x;
         const int v = (int)v0;
         bool found = false;
         if (v < g.n && depth[v] < 0) {
             const int end = g.row_ptr[v + 1];
-            for (int e = g.row_ptr[v]; e < end; e++) {
-                const int u = g.col[e];
-                ne++;
-                const bool in = IN_REP == kRepBoolmap ? (in_bool[u] != 0) : bit_test(in_bits, u);
-                if (in) { found = true; break; }
+            // parents probed kEdgeBatch at a time (their loads overlap); stop at
+            // the first parent in the input frontier, counting edges up to it
+            for (int e0 = g.row_ptr[v]; e0 < end && !found; e0 += kEdgeBatch) {
+                int uu[kEdgeBatch];
+                bool in[kEdgeBatch];
+#pragma unroll
+                for (int b = 0; b < kEdgeBatch; b++) uu[b] = g.col[e0 + b < end ? e0 + b : end - 1];
+#pragma unroll
+                for (int b = 0; b < kEdgeBatch; b++)
+                    in[b] = IN_REP == kRepBoolmap ? (in_bool[uu[b]] != 0) : bit_test(in_bits, uu[b]);
+#pragma unroll
+                for (int b = 0; b < kEdgeBatch; b++) {
+                    if (!found && e0 + b < end) {
+                        ne++;
+                        found = in[b];
+                    }
+                }
             }
             if (found) depth[v] = next;
         }
         if constexpr (OUT == kCreateFused) {
-            wave_append(out.q, out.count, out.cap, out.overflow, found, v);
+            emit_staged<kCreateFused, kDedupNone>(out, s_st, found, v);
+            emit_flush<kCreateFused>(out, s_st);
         } else {
             const uint64_t word = __ballot(found);
             if constexpr (OUT == kCreateBitmap) {
-                if (lane_id() == 0) out.bitmap[v0 >> 6] = word;
+                if (lane_id() == 0 && v0 < ((long long)g.n + 63) / 64 * 64) out.bitmap[v0 >> 6] = word;
             } else {
                 if (v < g.n) out.boolmap[v] = found ? 1 : 0;
             }
-            if (lane_id() == 0 && word) atomic_add_i32(out.count, __popcll(word));
+            found_cnt += found ? 1 : 0;
         }
+    }
+    if constexpr (OUT != kCreateFused) {
+        const int wsum = wave_sum(found_cnt);
+        if (lane_id() == 0 && wsum) atomicAdd(&s_cnt, wsum);
+        __syncthreads();
+        if (threadIdx.x == 0 && s_cnt) atomic_add_i32(out.count, s_cnt);
     }
 }
 

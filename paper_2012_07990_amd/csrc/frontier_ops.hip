@@ -89,14 +89,22 @@ void bitmap_to_boolmap(Ctx &c, const unsigned long long *src, int n, uint8_t *ds
     c.launches++;
 }
 
-// ---- dense -> queue (wave-ballot compaction, one atomic per wave) -------------------------
+// ---- dense -> queue (ballot compaction staged per workgroup: one global atomic per flush)
 __global__ __launch_bounds__(kBlock) void k_boolmap_to_queue(const uint8_t *map, int n, int32_t *q,
                                                              int32_t *count) {
+    __shared__ StageLDS s_st;
+    if (threadIdx.x == 0) s_st.c = 0;
+    __syncthreads();
+    OutFrontier o{};
+    o.q = q;
+    o.count = count;
+    o.cap = n;  // a set never exceeds n
+    o.overflow = count;
     const long long stride = (long long)gridDim.x * kBlock;
-    const long long nr = ((long long)n + kWave - 1) / kWave * kWave;
-    for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < nr; v += stride) {
-        const bool on = v < n && map[v];
-        wave_append(q, count, n, count, on, (int)v);  // cap n: a set never exceeds n
+    for (long long base = (long long)blockIdx.x * kBlock; base < n; base += stride) {
+        const long long v = base + threadIdx.x;
+        emit_staged<kCreateFused, kDedupNone>(o, s_st, v < n && map[v], (int)v);
+        if ((base / stride) % 8 == 7 || base + stride >= n) emit_flush<kCreateFused>(o, s_st);
     }
 }
 // one lane per 64-bit word: each lane writes its word's set bits in order

@@ -124,6 +124,15 @@ __device__ __forceinline__ void far_min_dev(const int32_t *farq, int fc, const i
 __device__ __forceinline__ void far_split_dev(const int32_t *farq, int fc, const int32_t *dist, int delta, int knew,
                                               const OutFrontier &near, int32_t *nfarq, int32_t *nfarc, int far_cap,
                                               int32_t *far_tag, int far_id, int32_t *flags, Tid t) {
+    // appends staged per workgroup (one global atomic per queue and flush)
+    __shared__ StageLDS s_near, s_far;
+    if (threadIdx.x == 0) { s_near.c = 0; s_far.c = 0; }
+    __syncthreads();
+    OutFrontier fo{};
+    fo.q = nfarq;
+    fo.count = nfarc;
+    fo.cap = far_cap;
+    fo.overflow = flags + 1;
     const int stride = t.nblocks * kBlock;
     const int n_iter = (fc + stride - 1) / stride;
     for (int it = 0; it < n_iter; it++) {
@@ -136,8 +145,12 @@ __device__ __forceinline__ void far_split_dev(const int32_t *farq, int fc, const
             if (b == knew) to_near = dedup_first<kDedupMonotonic>(near, v);
             else if (b > knew) to_far = atomic_max_i32(&far_tag[v], far_id) < far_id;
         }
-        wave_append(near.q, near.count, near.cap, near.overflow, to_near, v);
-        wave_append(nfarq, nfarc, far_cap, flags + 1, to_far, v);
+        emit_staged<kCreateFused, kDedupNone>(near, s_near, to_near, v);
+        emit_staged<kCreateFused, kDedupNone>(fo, s_far, to_far, v);
+        if (it % 8 == 7 || it == n_iter - 1) {
+            emit_flush<kCreateFused>(near, s_near);
+            emit_flush<kCreateFused>(fo, s_far);
+        }
     }
 }
 
