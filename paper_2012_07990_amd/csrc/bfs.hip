@@ -127,8 +127,8 @@ __global__ __launch_bounds__(kBlock) void k_bfs_fused(FusedBfsArgs a) {
             BfsPush f{a.depth, it + 1};
             if constexpr (LB == GG_LB_VERTEX_BASED) lb_vp<kCreateFused, kDedupNone>(a.g, src, f, o, t, ne);
             else if constexpr (LB == GG_LB_WM) lb_wm<kCreateFused, kDedupNone>(a.g, src, f, o, t, ne);
-            else if constexpr (LB == GG_LB_CM) lb_cm<kCreateFused, kDedupNone>(a.g, src, f, o, t, ne);
-            else lb_etwc<kCreateFused, kDedupNone>(a.g, src, f, o, t, ne);
+            else if constexpr (LB == GG_LB_CM) lb_cm<kCreateFused, kDedupNone, false>(a.g, src, f, o, t, ne);
+            else lb_etwc<kCreateFused, kDedupNone, false>(a.g, src, f, o, t, ne);
         } else {
             pulls++;
             // dense input map from the queue: clear, barrier, scatter, barrier

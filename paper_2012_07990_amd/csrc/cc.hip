@@ -96,8 +96,8 @@ __global__ __launch_bounds__(kBlock) void k_cc_fused(FusedCcArgs a) {
         CcHook f{a.label, changed};
         if constexpr (LB == GG_LB_VERTEX_BASED) lb_vp<kCreateBoolmap, kDedupNone>(a.g, src, f, o, t, ne);
         else if constexpr (LB == GG_LB_WM) lb_wm<kCreateBoolmap, kDedupNone>(a.g, src, f, o, t, ne);
-        else if constexpr (LB == GG_LB_CM) lb_cm<kCreateBoolmap, kDedupNone>(a.g, src, f, o, t, ne);
-        else lb_etwc<kCreateBoolmap, kDedupNone>(a.g, src, f, o, t, ne);
+        else if constexpr (LB == GG_LB_CM) lb_cm<kCreateBoolmap, kDedupNone, false>(a.g, src, f, o, t, ne);
+        else lb_etwc<kCreateBoolmap, kDedupNone, false>(a.g, src, f, o, t, ne);
         if (!grid_sync(bar)) break;
         cc_compress_dev(a.label, a.g.n, t);
         if (!grid_sync(bar)) break;

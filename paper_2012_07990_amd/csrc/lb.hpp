@@ -127,13 +127,16 @@ __device__ __forceinline__ int block_excl_scan(int x, int &excl, int *s_tmp /* k
 }
 
 // ---------------------------------------------------------------------------- CM
-template <int CREATE, int DEDUP, class Src, class F>
+// STAGE: appends staged per workgroup (the default); the persistent kernels
+// on high-diameter graphs, whose few workgroups rarely contend, append per
+// wavefront instead and skip the flush barriers
+template <int CREATE, int DEDUP, bool STAGE = true, class Src, class F>
 __device__ void lb_cm(const DevGraph &g, const Src &src, F &f, const OutFrontier &out, Tid t,
                       long long &ne) {
     __shared__ int s_u[kBlock], s_beg[kBlock], s_scan[kBlock], s_tmp[kBlock / kWave];
     __shared__ StageLDS s_st;
     if (threadIdx.x == 0) s_st.c = 0;
-    f.begin();
+    if constexpr (STAGE) f.begin();
     __syncthreads();
     for (int base = t.block * kBlock; base < src.size; base += t.nblocks * kBlock) {
         const int i = base + (int)threadIdx.x;
@@ -152,17 +155,20 @@ __device__ void lb_cm(const DevGraph &g, const Src &src, F &f, const OutFrontier
             if (f.done(uu)) continue;
             const int e = s_beg[k] + (j - s_scan[k]);
             const int x = f.edge(uu, g.col[e], e);
-            emit_staged<CREATE, DEDUP>(out, s_st, x >= 0, x);
+            if constexpr (STAGE) emit_staged<CREATE, DEDUP>(out, s_st, x >= 0, x);
+            else emit<CREATE, DEDUP>(out, x >= 0, x);
             ne++;
         }
         __syncthreads();
-        emit_flush<CREATE>(out, s_st);
-        f.flush();
+        if constexpr (STAGE) {
+            emit_flush<CREATE>(out, s_st);
+            f.flush();
+        }
     }
 }
 
 // ---------------------------------------------------------------------------- ETWC
-template <int CREATE, int DEDUP, class Src, class F>
+template <int CREATE, int DEDUP, bool STAGE = true, class Src, class F>
 __device__ void lb_etwc(const DevGraph &g, const Src &src, F &f, const OutFrontier &out, Tid t,
                         long long &ne) {
     // Q[0] lane stage, Q[1] wave stage, Q[2] workgroup stage: {begin, end, vertex}
@@ -171,7 +177,7 @@ __device__ void lb_etwc(const DevGraph &g, const Src &src, F &f, const OutFronti
     __shared__ StageLDS s_st;
     const int tid = threadIdx.x, lane = lane_id(), wib = tid / kWave;
     if (tid == 0) s_st.c = 0;
-    f.begin();
+    if constexpr (STAGE) f.begin();
     __syncthreads();
     for (int base = t.block * kBlock; base < src.size; base += t.nblocks * kBlock) {
         if (tid < 3) q_n[tid] = 0;
@@ -216,7 +222,8 @@ __device__ void lb_etwc(const DevGraph &g, const Src &src, F &f, const OutFronti
                 for (int b = 0; b < kEdgeBatch; b++) {
                     if (e0 + b < end && !f.done(u)) {
                         const int x = f.apply(u, vv[b], e0 + b, pp[b]);
-                        emit_staged<CREATE, DEDUP>(out, s_st, x >= 0, x);
+                        if constexpr (STAGE) emit_staged<CREATE, DEDUP>(out, s_st, x >= 0, x);
+                        else emit<CREATE, DEDUP>(out, x >= 0, x);
                         ne++;
                     }
                 }
@@ -228,7 +235,8 @@ __device__ void lb_etwc(const DevGraph &g, const Src &src, F &f, const OutFronti
             for (int e = q_beg[1][k] + lane; e < end; e += kWave) {
                 if (f.done(u)) break;
                 const int x = f.edge(u, g.col[e], e);
-                emit_staged<CREATE, DEDUP>(out, s_st, x >= 0, x);
+                if constexpr (STAGE) emit_staged<CREATE, DEDUP>(out, s_st, x >= 0, x);
+                else emit<CREATE, DEDUP>(out, x >= 0, x);
                 ne++;
             }
         }
@@ -238,13 +246,16 @@ __device__ void lb_etwc(const DevGraph &g, const Src &src, F &f, const OutFronti
             for (int e = q_beg[2][k] + tid; e < end; e += kBlock) {
                 if (f.done(u)) break;
                 const int x = f.edge(u, g.col[e], e);
-                emit_staged<CREATE, DEDUP>(out, s_st, x >= 0, x);
+                if constexpr (STAGE) emit_staged<CREATE, DEDUP>(out, s_st, x >= 0, x);
+                else emit<CREATE, DEDUP>(out, x >= 0, x);
                 ne++;
             }
         }
         __syncthreads();
-        emit_flush<CREATE>(out, s_st);
-        f.flush();
+        if constexpr (STAGE) {
+            emit_flush<CREATE>(out, s_st);
+            f.flush();
+        }
     }
 }
 

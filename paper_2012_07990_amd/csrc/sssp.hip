@@ -204,13 +204,12 @@ __global__ __launch_bounds__(kBlock) void k_sssp_fused(FusedSsspArgs a) {
         int32_t *farq = (fe & 1) ? a.farq1 : a.farq0;
         int32_t *farc = a.ctr + 3 + (fe & 1);
         if (cnt > 0) {
-            SsspRelaxT<LB == GG_LB_CM || LB == GG_LB_ETWC> f{a.dist, a.g.w, (long long)(k + 1) * a.delta, farq, farc,
-                                                            a.g.n, a.far_tag, fe + 1, flags};
+            SsspRelax f{a.dist, a.g.w, (long long)(k + 1) * a.delta, farq, farc, a.g.n, a.far_tag, fe + 1, flags};
             const SrcQueue src{qin, cnt};
             if constexpr (LB == GG_LB_VERTEX_BASED) lb_vp<kCreateFused, kDedupMonotonic>(a.g, src, f, o, t, ne);
             else if constexpr (LB == GG_LB_WM) lb_wm<kCreateFused, kDedupMonotonic>(a.g, src, f, o, t, ne);
-            else if constexpr (LB == GG_LB_CM) lb_cm<kCreateFused, kDedupMonotonic>(a.g, src, f, o, t, ne);
-            else lb_etwc<kCreateFused, kDedupMonotonic>(a.g, src, f, o, t, ne);
+            else if constexpr (LB == GG_LB_CM) lb_cm<kCreateFused, kDedupMonotonic, false>(a.g, src, f, o, t, ne);
+            else lb_etwc<kCreateFused, kDedupMonotonic, false>(a.g, src, f, o, t, ne);
             rounds++;
         } else {
             const int fc = load_relaxed(farc);
