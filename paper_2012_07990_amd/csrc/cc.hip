@@ -32,7 +32,10 @@ struct CcHook {
         if (lu != lv) {
             const int hi = lu > lv ? lu : lv, lo = lu > lv ? lv : lu;
             if (hi != m_hi || lo < m_lo) {
-                ch = atomic_min_i32(&label[hi], lo) > lo;
+                // a plain read first: labels hit by many hooks (component roots)
+                // drop early, and later hooks see that and skip the atomic
+                // (a stale, larger read only costs the atomic)
+                if (label[hi] > lo) ch = atomic_min_i32(&label[hi], lo) > lo;
                 m_hi = hi;
                 m_lo = lo;
             }
