@@ -32,15 +32,21 @@ struct OutFrontier {
     unsigned *dedup_bytes;   // BOOLMAP dedup, bytes packed 4 per word (cleared every round)
 };
 
+// Each test reads the tag first and skips the atomic when v is already
+// marked (tags and bits only grow within a round; a stale read only costs the
+// atomic), which keeps repeated enqueues of popular vertices off one address.
 template <int DEDUP>
 __device__ __forceinline__ bool dedup_first(const OutFrontier &o, int v) {
     if constexpr (DEDUP == kDedupMonotonic) {
+        if (o.tags[v] >= o.iter) return false;
         return atomic_max_i32(&o.tags[v], o.iter) < o.iter;
     } else if constexpr (DEDUP == kDedupBitmap) {
         const unsigned long long bit = 1ull << (v & 63);
+        if (o.dedup_bits[v >> 6] & bit) return false;
         return (atomic_or_u64(&o.dedup_bits[v >> 6], bit) & bit) == 0;
     } else if constexpr (DEDUP == kDedupBoolmap) {
         const unsigned sh = (unsigned)(v & 3) * 8u;
+        if ((o.dedup_bytes[v >> 2] >> sh) & 1u) return false;
         return ((atomic_or_u32(&o.dedup_bytes[v >> 2], 1u << sh) >> sh) & 1u) == 0;
     } else {
         return true;

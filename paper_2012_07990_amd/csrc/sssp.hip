@@ -57,7 +57,7 @@ struct SsspRelaxT {
             const int old = atomic_min_i32(&dist[v], (int)nd);
             if (nd < old) {
                 if (nd < bucket_end) to_near = true;
-                else to_far = atomic_max_i32(&far_tag[v], far_id) < far_id;
+                else to_far = far_tag[v] < far_id && atomic_max_i32(&far_tag[v], far_id) < far_id;
             }
         }
         if constexpr (STAGE) stage_append(sssp_far_stage(farq, farc), far_cap, flags + 1, to_far, v);
