@@ -201,12 +201,16 @@ __device__ __forceinline__ double bc_term(const DevGraph &g, int e, int dv1, dou
 
 // The terms of edges e0, e0 + stride, ... below e_end, in that order, with the
 // loads of kEdgeBatch edges issued before their steps (the order of the
-// steps, and so the rounding, is the plain loop's).
-__device__ __forceinline__ double bc_terms(const DevGraph &g, int e0, int e_end, int stride, int dv1, double sv,
-                                           const int32_t *depth, const unsigned long long *sigma,
+// steps, and so the rounding, is the plain loop's). DT: the depth array read
+// for the successor test (one byte per vertex when the levels fit, so the
+// array stays in L2).
+template <class DT>
+__device__ __forceinline__ double bc_terms(const DevGraph &g, int e0, int e_end, int stride, DT dv1, double sv,
+                                           const DT *depth, const unsigned long long *sigma,
                                            const double *delta, double acc) {
     for (int e = e0; e < e_end; e += kEdgeBatch * stride) {
-        int ww[kEdgeBatch], dd[kEdgeBatch];
+        int ww[kEdgeBatch];
+        DT dd[kEdgeBatch];
         double sg[kEdgeBatch], dl[kEdgeBatch];
 #pragma unroll
         for (int b = 0; b < kEdgeBatch; b++) {
@@ -228,8 +232,10 @@ __device__ __forceinline__ double bc_terms(const DevGraph &g, int e0, int e_end,
     return acc;
 }
 
+// the vertices of level L (ids in level_ids); dv1 = L + 1 in the type of dep
+template <class DT>
 __global__ __launch_bounds__(kBlock) void k_bc_backward(DevGraph g, const int32_t *level_ids, int count,
-                                                        const int32_t *depth, const unsigned long long *sigma,
+                                                        const DT *dep, DT dv1, const unsigned long long *sigma,
                                                         double *delta, int src) {
     __shared__ int q_v[2][kBlock];
     __shared__ int q_n[2];
@@ -245,9 +251,8 @@ __global__ __launch_bounds__(kBlock) void k_bc_backward(DevGraph g, const int32_
             if (v == src) {
                 delta[v] = 0.0;
             } else if (deg < kBcWaveDeg) {
-                const int dv1 = depth[v] + 1;
                 const double sv = (double)sigma[v];
-                delta[v] = bc_terms(g, g.row_ptr[v], g.row_ptr[v + 1], 1, dv1, sv, depth, sigma, delta, 0.0);
+                delta[v] = bc_terms(g, g.row_ptr[v], g.row_ptr[v + 1], 1, dv1, sv, dep, sigma, delta, 0.0);
             } else {
                 const int k = atomicAdd(&q_n[deg < kBcBlockDeg ? 0 : 1], 1);
                 q_v[deg < kBcBlockDeg ? 0 : 1][k] = v;
@@ -256,17 +261,15 @@ __global__ __launch_bounds__(kBlock) void k_bc_backward(DevGraph g, const int32_
         __syncthreads();
         for (int k = wib; k < q_n[0]; k += kBlock / kWave) {
             const int v = q_v[0][k];
-            const int dv1 = depth[v] + 1;
             const double sv = (double)sigma[v];
-            double acc = bc_terms(g, g.row_ptr[v] + lane, g.row_ptr[v + 1], kWave, dv1, sv, depth, sigma, delta, 0.0);
+            double acc = bc_terms(g, g.row_ptr[v] + lane, g.row_ptr[v + 1], kWave, dv1, sv, dep, sigma, delta, 0.0);
             acc = wave_sum(acc);
             if (lane == 0) delta[v] = acc;
         }
         for (int k = 0; k < q_n[1]; k++) {
             const int v = q_v[1][k];
-            const int dv1 = depth[v] + 1;
             const double sv = (double)sigma[v];
-            double acc = bc_terms(g, g.row_ptr[v] + tid, g.row_ptr[v + 1], kBlock, dv1, sv, depth, sigma, delta, 0.0);
+            double acc = bc_terms(g, g.row_ptr[v] + tid, g.row_ptr[v + 1], kBlock, dv1, sv, dep, sigma, delta, 0.0);
             acc = wave_sum(acc);
             __syncthreads();
             if (lane == 0) s_w[wib] = acc;
@@ -278,6 +281,14 @@ __global__ __launch_bounds__(kBlock) void k_bc_backward(DevGraph g, const int32_
             }
         }
         __syncthreads();
+    }
+}
+
+// one-byte copy of the BFS depths (255 = unreached) when every level fits
+__global__ __launch_bounds__(kBlock) void k_depth8(const int32_t *depth, int n, uint8_t *d8) {
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
+        const int d = depth[v];
+        d8[v] = d < 0 ? (uint8_t)255 : (uint8_t)d;
     }
 }
 
@@ -360,10 +371,21 @@ void bc_run(Graph &G, int32_t src, const gg_schedule &sch, uint64_t *sigma_out, 
     require(ws->h_i32.p[3] == 0, GG_ERR_OVERFLOW, "a shortest-path count exceeds 2^64-1");
     // backward, deepest level first (the deepest level's delta stays 0)
     const int levels = (int)off.size() - 2;
+    const bool small = levels < 255;  // depths 0..254 fit a byte next to the 255 marker
+    uint8_t *d8 = ws->boolmap[0].p;   // free after the forward pass (nb >= n bytes)
+    if (small) {
+        hipLaunchKernelGGL(k_depth8, dim3(blocks_for(n, kBlock, 8192)), dim3(kBlock), 0, c.s, depth, n, d8);
+        GG_CHECK_LAUNCH();
+        c.launches++;
+    }
     for (int L = levels - 2; L >= 0; L--) {
         const int cnt = off[L + 1] - off[L];
-        hipLaunchKernelGGL(k_bc_backward, dim3(blocks_for(cnt, kBlock, 16384)), dim3(kBlock), 0, c.s, g,
-                           order + off[L], cnt, depth, sigma, delta, src);
+        if (small)
+            hipLaunchKernelGGL(k_bc_backward<uint8_t>, dim3(blocks_for(cnt, kBlock, 16384)), dim3(kBlock), 0, c.s, g,
+                               order + off[L], cnt, (const uint8_t *)d8, (uint8_t)(L + 1), sigma, delta, src);
+        else
+            hipLaunchKernelGGL(k_bc_backward<int32_t>, dim3(blocks_for(cnt, kBlock, 16384)), dim3(kBlock), 0, c.s, g,
+                               order + off[L], cnt, (const int32_t *)depth, (int32_t)(L + 1), sigma, delta, src);
         GG_CHECK_LAUNCH();
         c.launches++;
     }
