@@ -53,7 +53,12 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--only", default="", help="comma list of algorithms to run (bfs,sssp,cc,pr,bc)")
     p.add_argument("--sweep", action="store_true", help="time every schedule family per algorithm")
-    p.add_argument("--sweep-filter", default="", help="comma list of substrings: only sweep schedules matching one")
+    p.add_argument("--sweep-filter", default="",
+                   help="comma list of substrings of 'algo/schedule': only sweep schedules matching one")
+    p.add_argument("--counters-sweep", action="store_true",
+                   help="for rocprofv3 --pmc runs: run each (filtered) sweep schedule twice after a warm run, "
+                        "bracketed by marker launches (a one-element torch.cumsum before and after), print "
+                        "the schedule order and exit")
     p.add_argument("--verbose", action="store_true")
     p.add_argument("--no-batched", action="store_true", help="skip the batched multi-source section")
     p.add_argument("--no-serving", action="store_true", help="skip the serving section")
@@ -81,7 +86,7 @@ def schedules(gg):
     bfs.s1.load_balance = gg.LB_STRICT
     bfs.threshold = 0.01
     sssp = gg.make_schedule(lb="strict", delta=4096)
-    cc = gg.make_schedule(lb="etwc")
+    cc = gg.make_schedule(lb="edge_only")
     pr = gg.make_schedule(lb="strict", direction=gg.PULL, edge_blocking=True, blocking_size=PR_SEGMENT)
     bc = gg.schedule_preset(gg.ALGO_BC, gg.PRESET_POWERLAW)
     bc.s1.load_balance = gg.LB_STRICT
@@ -187,6 +192,32 @@ def main():
             return G.pagerank(s, iters=20, stats=stats)
         return G.bc(src, s, stats=stats)
 
+    if args.counters_sweep:
+        marker = torch.ones(1, device="cuda")
+        order = []
+        for a, d in sweep_schedules(gg).items():
+            if a not in algos:
+                continue
+            for name, s in d.items():
+                if args.sweep_filter and not any(f in "%s/%s" % (a, name) for f in args.sweep_filter.split(",")):
+                    continue
+                try:
+                    run(a, s)
+                    torch.cuda.synchronize()
+                except gg.GGError:
+                    continue
+                torch.cumsum(marker, 0)
+                torch.cuda.synchronize()
+                for _ in range(2):
+                    run(a, s)
+                torch.cuda.synchronize()
+                torch.cumsum(marker, 0)
+                torch.cuda.synchronize()
+                order.append("%s/%s" % (a, name))
+        print(json.dumps({"counters_sweep": order, "runs_per_schedule": 2}), flush=True)
+        G.close()
+        return
+
     # traversed-edge numerators from one verified run of each algorithm
     reached = None
     edges = {}
@@ -209,7 +240,7 @@ def main():
             if a not in algos:
                 continue
             for name, s in d.items():
-                if args.sweep_filter and not any(f in name for f in args.sweep_filter.split(",")):
+                if args.sweep_filter and not any(f in "%s/%s" % (a, name) for f in args.sweep_filter.split(",")):
                     continue
                 try:
                     run(a, s)
