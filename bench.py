@@ -69,6 +69,9 @@ def parse():
                    help="also time BFS/SSSP on a WxW road-like grid (fused vs unfused, delta sweep)")
     p.add_argument("--grid-deltas", default="1,8,64,512",
                    help="delta values of the grid SSSP runs (an unfused run is skipped when the fused one took > 20 s)")
+    p.add_argument("--tune", action="store_true",
+                   help="also run the autotuner per algorithm on R-MAT 22 and report its picks beside the step's schedules")
+    p.add_argument("--tune-budget-s", type=float, default=8.0, help="autotuner wall-clock budget per algorithm")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy three times (scales rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     p.add_argument("--serve-full", action="store_true",
@@ -331,12 +334,15 @@ def main():
                 "per_launch_ms": round(per_launch_ms, 5), "bytes_per_launch": round(alg_bytes),
                 "launches_per_round": launches_per_round, "row_segment_pairs": pairs}
 
+    tuned = tune_section(gg, G, scheds, run, src, edges, torch, args) if args.tune else None
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(g, src, reached_edges)
     G.close()
     del G
 
+    small = small_section(gg, graphgen, torch)
     grid = grid_section(gg, graphgen, torch, args.grid, [int(x) for x in args.grid_deltas.split(",")]) \
         if args.grid else None
     batched = None if args.no_batched else batched_section(gg, graphgen, torch)
@@ -353,11 +359,92 @@ def main():
         "per_algo": per,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "small": small,
+        "tuned": tuned,
         "grid": grid,
         "batched": batched,
         "serving": serving,
     }
     print(json.dumps(rec), flush=True)
+
+
+def describe(gg, s):
+    """Short text form of a schedule."""
+    lb = {v: k for k, v in gg.LB_NAMES.items() if k != "vertex_based"}
+
+    def one(x):
+        t = "%s %s" % ("pull" if x.direction == gg.PULL else "push", lb.get(x.load_balance, x.load_balance))
+        if x.direction == gg.PULL:
+            t += " " + ("bitmap" if x.pull_rep == gg.REP_BITMAP else "boolmap")
+        if x.delta > 1:
+            t += " delta=%d" % x.delta
+        if x.edge_blocking:
+            t += " EB(%d)" % x.blocking_size
+        if x.kernel_fusion:
+            t += " fused"
+        return t
+    return one(s.s1) + (" | hybrid theta=%g -> %s" % (s.threshold, one(s.s2)) if s.hybrid else "")
+
+
+def small_section(gg, graphgen, torch):
+    """R-MAT 14 BFS with the plain vertex-parallel push schedule: a latency-bound
+    traversal (the whole graph fits in L2)."""
+    g = graphgen.rmat(14)
+    G = gg.Graph.from_graphgen(g)
+    src = graphgen.max_degree_vertex(g)
+    hyb = gg.schedule_preset(gg.ALGO_BFS, gg.PRESET_POWERLAW)
+    hyb.s1.load_balance = gg.LB_STRICT
+    hyb.threshold = 0.01
+    rec = {"workload": "rmat14 BFS from the highest-degree vertex %d (degree %d)" % (src, g.degrees()[src]),
+           "n": g.n, "m": g.m}
+    for key, s in [("push_vp", gg.make_schedule(lb="vp")), ("push_strict", gg.make_schedule(lb="strict")),
+                   ("hybrid_strict", hyb)]:
+        G.bfs(src, s)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(20):
+            st = gg.Stats()
+            t1 = time.perf_counter()
+            d = G.bfs(src, s, stats=st)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t1)
+        ms = 1e3 * sorted(ts)[len(ts) // 2]
+        edges = int(g.degrees()[d.cpu().numpy() >= 0].sum())
+        rec[key] = {"schedule": describe(gg, s), "ms": round(ms, 4), "gteps": round(edges / ms / 1e6, 3),
+                    "levels": st.iterations, "us_per_level": round(1e3 * ms / max(st.iterations, 1), 2),
+                    "launches": st.launches}
+    G.close()
+    log("small: %s" % rec)
+    return rec
+
+
+def tune_section(gg, G, scheds, run, src, edges, torch, args):
+    """The autotuner's pick per algorithm (fixed wall-clock budget) against the
+    step's hand-picked schedule, both timed the same way."""
+    algo_id = {"bfs": gg.ALGO_BFS, "sssp": gg.ALGO_SSSP, "cc": gg.ALGO_CC, "pr": gg.ALGO_PR, "bc": gg.ALGO_BC}
+
+    def timed(a, s):
+        run(a, s)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            t1 = time.perf_counter()
+            run(a, s)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t1)
+        return 1e3 * sorted(ts)[1]
+
+    out = {"budget_s": args.tune_budget_s, "algos": {}}
+    for a in ["bfs", "sssp", "cc", "pr", "bc"]:
+        t0 = time.perf_counter()
+        s, best = G.autotune(algo_id[a], args.tune_budget_s, [src])
+        took = time.perf_counter() - t0
+        ms_t, ms_h = timed(a, s), timed(a, scheds[a])
+        rec = {"tuned": describe(gg, s), "tuned_ms": round(ms_t, 3), "bench_schedule": describe(gg, scheds[a]),
+               "bench_ms": round(ms_h, 3), "tuner_s": round(took, 1)}
+        log("tune %s: %s" % (a, rec))
+        out["algos"][a] = rec
+    return out
 
 
 def grid_section(gg, graphgen, torch, W, deltas):
