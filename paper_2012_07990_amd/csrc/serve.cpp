@@ -72,7 +72,7 @@ struct GpuExecutor : serve::Executor {
         if (algo == GG_ALGO_BFS && G.m < 8ll * G.n) s = default_schedule();
         // wider buckets on sparse high-diameter graphs: fewer rounds, each of
         // which costs a grid barrier, against some re-relaxed edges
-        if (algo == GG_ALGO_SSSP) s.s1.delta = G.m < 8ll * G.n ? 512 : 64;
+        if (algo == GG_ALGO_SSSP) s.s1.delta = G.m < 8ll * G.n ? 4096 : 64;
         if (algo == GG_ALGO_SSSP && !G.has_weights) s = default_schedule();
         return s;
     }
