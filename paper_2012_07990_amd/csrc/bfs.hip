@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kBlock) void k_bfs_fused(FusedBfsArgs a) {
         if (!pull) {
             const SrcQueue src{qin, cnt};
             BfsPush f{a.depth, it + 1};
-            if constexpr (LB == GG_LB_VERTEX_BASED) lb_vp<kCreateFused, kDedupNone>(a.g, src, f, o, t, ne);
+            if constexpr (LB == GG_LB_VERTEX_BASED) lb_vp<kCreateFused, kDedupNone, false>(a.g, src, f, o, t, ne);
             else if constexpr (LB == GG_LB_WM) lb_wm<kCreateFused, kDedupNone>(a.g, src, f, o, t, ne);
             else if constexpr (LB == GG_LB_CM) lb_cm<kCreateFused, kDedupNone, false>(a.g, src, f, o, t, ne);
             else lb_etwc<kCreateFused, kDedupNone, false>(a.g, src, f, o, t, ne);

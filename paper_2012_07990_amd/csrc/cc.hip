@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kBlock) void k_cc_fused(FusedCcArgs a) {
         if (t.block == 0 && threadIdx.x == 0)
             __hip_atomic_store(a.ctr + ((r + 1) % 3), 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         CcHook f{a.label, changed};
-        if constexpr (LB == GG_LB_VERTEX_BASED) lb_vp<kCreateBoolmap, kDedupNone>(a.g, src, f, o, t, ne);
+        if constexpr (LB == GG_LB_VERTEX_BASED) lb_vp<kCreateBoolmap, kDedupNone, false>(a.g, src, f, o, t, ne);
         else if constexpr (LB == GG_LB_WM) lb_wm<kCreateBoolmap, kDedupNone>(a.g, src, f, o, t, ne);
         else if constexpr (LB == GG_LB_CM) lb_cm<kCreateBoolmap, kDedupNone, false>(a.g, src, f, o, t, ne);
         else lb_etwc<kCreateBoolmap, kDedupNone, false>(a.g, src, f, o, t, ne);

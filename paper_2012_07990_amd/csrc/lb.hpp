@@ -43,19 +43,44 @@ struct Tid {  // position of this lane in the (possibly persistent) grid
 };
 
 // ---------------------------------------------------------------------------- VP
-template <int CREATE, int DEDUP, class Src, class F>
+// One lane per frontier vertex walks its edges, loading kEdgeBatch edges at a
+// time; appends are staged per workgroup unless STAGE is false (see lb_cm).
+template <int CREATE, int DEDUP, bool STAGE = true, class Src, class F>
 __device__ void lb_vp(const DevGraph &g, const Src &src, F &f, const OutFrontier &out, Tid t,
                       long long &ne) {
+    __shared__ StageLDS s_st;
+    if constexpr (STAGE) {
+        if (threadIdx.x == 0) s_st.c = 0;
+        f.begin();
+        __syncthreads();
+    }
     const int stride = t.nblocks * kBlock;
-    for (int i = t.block * kBlock + (int)threadIdx.x; i < src.size; i += stride) {
-        const int u = src.get(i);
-        if (!f.active(u)) continue;
-        const int end = g.row_ptr[u + 1];
-        for (int e = g.row_ptr[u]; e < end; e++) {
-            const int x = f.edge(u, g.col[e], e);
-            emit<CREATE, DEDUP>(out, x >= 0, x);
-            ne++;
-            if (f.done(u)) break;
+    for (int base = t.block * kBlock; base < src.size; base += stride) {
+        const int i = base + (int)threadIdx.x;
+        const int u = i < src.size ? src.get(i) : 0;
+        if (i < src.size && f.active(u)) {
+            const int end = g.row_ptr[u + 1];
+            for (int e0 = g.row_ptr[u]; e0 < end && !f.done(u); e0 += kEdgeBatch) {
+                int vv[kEdgeBatch];
+                typename F::Pre pp[kEdgeBatch];
+#pragma unroll
+                for (int b = 0; b < kEdgeBatch; b++) vv[b] = g.col[e0 + b < end ? e0 + b : end - 1];
+#pragma unroll
+                for (int b = 0; b < kEdgeBatch; b++) pp[b] = f.load(u, vv[b], e0 + b < end ? e0 + b : end - 1);
+#pragma unroll
+                for (int b = 0; b < kEdgeBatch; b++) {
+                    if (e0 + b < end && !f.done(u)) {
+                        const int x = f.apply(u, vv[b], e0 + b, pp[b]);
+                        if constexpr (STAGE) emit_staged<CREATE, DEDUP>(out, s_st, x >= 0, x);
+                        else emit<CREATE, DEDUP>(out, x >= 0, x);
+                        ne++;
+                    }
+                }
+            }
+        }
+        if constexpr (STAGE) {
+            emit_flush<CREATE>(out, s_st);
+            f.flush();
         }
     }
 }

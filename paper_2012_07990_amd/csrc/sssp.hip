@@ -27,7 +27,7 @@ __device__ __forceinline__ Staged sssp_far_stage(int32_t *farq, int32_t *farc) {
 }
 
 // STAGE: far appends are staged per workgroup (the load balancer calls
-// begin() and flush() at workgroup-uniform points: CM, ETWC and STRICT do)
+// begin() and flush() at workgroup-uniform points: VP, CM, ETWC and STRICT do)
 template <bool STAGE>
 struct SsspRelaxT {
     int32_t *dist;
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_sssp_fused(FusedSsspArgs a) {
         if (cnt > 0) {
             SsspRelax f{a.dist, a.g.w, (long long)(k + 1) * a.delta, farq, farc, a.g.n, a.far_tag, fe + 1, flags};
             const SrcQueue src{qin, cnt};
-            if constexpr (LB == GG_LB_VERTEX_BASED) lb_vp<kCreateFused, kDedupMonotonic>(a.g, src, f, o, t, ne);
+            if constexpr (LB == GG_LB_VERTEX_BASED) lb_vp<kCreateFused, kDedupMonotonic, false>(a.g, src, f, o, t, ne);
             else if constexpr (LB == GG_LB_WM) lb_wm<kCreateFused, kDedupMonotonic>(a.g, src, f, o, t, ne);
             else if constexpr (LB == GG_LB_CM) lb_cm<kCreateFused, kDedupMonotonic, false>(a.g, src, f, o, t, ne);
             else lb_etwc<kCreateFused, kDedupMonotonic, false>(a.g, src, f, o, t, ne);
@@ -326,7 +326,7 @@ void sssp_run(Graph &G, int32_t src, const gg_schedule &sch, int32_t *dist, hipS
             OutFrontier o = fs.prep_out(s.frontier_creation, dd, iter++);
             const PushPlan plan{s.load_balance, s.frontier_creation, dd};
             const int lbm = s.load_balance;
-            if (lbm == GG_LB_STRICT || lbm == GG_LB_CM || lbm == GG_LB_ETWC) {
+            if (lbm == GG_LB_STRICT || lbm == GG_LB_CM || lbm == GG_LB_ETWC || lbm == GG_LB_VERTEX_BASED) {
                 SsspRelaxT<true> f{dist, g.w, (long long)(k + 1) * delta, farq[fe & 1], ctr + 16 + (fe & 1), n,
                                    ws->aux_i32[2].p, fe + 1, ctr + 20};
                 push_apply(c, g, *ws, plan, q, fs.count, f, o, member_map(*ws, n, s.load_balance));
