@@ -171,6 +171,17 @@ gg_status gg_graph_info(const gg_graph *g, int32_t *n, int64_t *m, int32_t *has_
 gg_status gg_graph_prepare_edgeblocking(gg_graph *g, int32_t seg_vertices, gg_stream_t stream,
                                         double *prep_ms);
 /*
+ * PULL EdgeBlocking layout (not in the paper; the gather-side counterpart of
+ * the paper's EdgeBlocking, used by PageRank PULL + STRICT with
+ * edge_blocking set): the CSR split by source segment [s*seg_vertices,
+ * (s+1)*seg_vertices) into S segment CSRs (rows keep their order) plus the
+ * STRICT chunk-to-row partition of each. Owned by the graph, cached per
+ * seg_vertices (a later gg_pagerank with that width reuses it). prep_ms (may
+ * be NULL) receives the build time on the device (0 when it was cached).
+ * Requires GG_SYMMETRIC.
+ */
+gg_status gg_graph_prepare_pull_blocking(gg_graph *g, int32_t seg_vertices, gg_stream_t stream, double *prep_ms);
+/*
  * Copy the blocked COO built by gg_graph_prepare_edgeblocking into caller
  * device buffers src_dev[m], dst_dev[m] and host seg_start[S+1]
  * (S = ceil(n / seg_vertices)); segment s holds entries [seg_start[s],

@@ -111,6 +111,7 @@ _sig("gg_graph_destroy", [_P])
 _sig("gg_graph_info", [_P, ctypes.POINTER(_i32), ctypes.POINTER(_i64), ctypes.POINTER(_i32),
                        ctypes.POINTER(_i32)])
 _sig("gg_graph_prepare_edgeblocking", [_P, _i32, _P, ctypes.POINTER(ctypes.c_double)])
+_sig("gg_graph_prepare_pull_blocking", [_P, _i32, _P, ctypes.POINTER(ctypes.c_double)])
 _sig("gg_graph_edgeblocking_export", [_P, _i32, _P, _P, _P, _P])
 _sig("gg_schedule_default", [_SP])
 _sig("gg_schedule_preset", [_i32, _i32, _SP])
@@ -398,6 +399,13 @@ class Graph:
         ms = ctypes.c_double()
         _check(_lib.gg_graph_prepare_edgeblocking(self.handle, int(seg_vertices), _stream(stream),
                                                   ctypes.byref(ms)), "gg_graph_prepare_edgeblocking")
+        return ms.value
+
+    def prepare_pull_blocking(self, seg_vertices: int, stream=None) -> float:
+        """Build (or reuse) the PULL EdgeBlocking layout; returns its build time in ms (0 if cached)."""
+        ms = ctypes.c_double()
+        _check(_lib.gg_graph_prepare_pull_blocking(self.handle, int(seg_vertices), _stream(stream),
+                                                   ctypes.byref(ms)), "gg_graph_prepare_pull_blocking")
         return ms.value
 
     def edgeblocking_export(self, seg_vertices: int):

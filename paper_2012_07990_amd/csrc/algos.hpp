@@ -33,6 +33,8 @@ void msbc_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &s, uint64
 gg_schedule autotune(Graph &G, int algo, double budget_s, const int32_t *probes, int nprobe, hipStream_t st,
                      double *best_ms);
 
+// PULL EdgeBlocking layout build (cached on the graph); returns device milliseconds, 0 if cached
+double pull_layout_prepare(Graph &G, int32_t seg_vertices, hipStream_t stream);
 // EdgeBlocking preprocessing; returns milliseconds
 double edgeblock_prepare(Ctx &c, Graph &G, int32_t seg_vertices);
 

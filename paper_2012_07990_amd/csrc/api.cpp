@@ -190,6 +190,16 @@ gg_status gg_graph_prepare_edgeblocking(gg_graph *g, int32_t seg_vertices, gg_st
     });
 }
 
+gg_status gg_graph_prepare_pull_blocking(gg_graph *g, int32_t seg_vertices, gg_stream_t stream, double *prep_ms) {
+    return guarded([&] {
+        check_graph(g);
+        require(seg_vertices >= 1, GG_ERR_INVALID_ARG, "seg_vertices must be >= 1");
+        require(g->g.symmetric, GG_ERR_INVALID_ARG, "PULL needs a symmetric graph (GG_SYMMETRIC)");
+        const double ms = pull_layout_prepare(g->g, seg_vertices, S(stream));
+        if (prep_ms) *prep_ms = ms;
+    });
+}
+
 gg_status gg_graph_edgeblocking_export(const gg_graph *g, int32_t seg_vertices, int32_t *src_dev, int32_t *dst_dev,
                                        int64_t *seg_start_host, gg_stream_t stream) {
     return guarded([&] {

@@ -353,13 +353,34 @@ __global__ __launch_bounds__(kBlock) void k_seg_count(DevGraph g, int N, int S, 
     }
 }
 
+// Copy each row's piece in segment s; pieces of 64 or more entries are copied
+// by a whole wavefront (a hub's piece would otherwise be one lane's loop).
 __global__ __launch_bounds__(kBlock) void k_seg_fill(DevGraph g, int N, int s, const int32_t *rp_s, int32_t *col_s) {
-    for (int v = blockIdx.x * kBlock + threadIdx.x; v < g.n; v += gridDim.x * kBlock) {
-        const int beg = g.row_ptr[v], end = g.row_ptr[v + 1];
-        const int lo = row_lower_bound(g.col, beg, end, (long long)s * N);
-        const int hi = row_lower_bound(g.col, lo, end, (long long)(s + 1) * N);
-        int32_t *dst = col_s + rp_s[v];
-        for (int e = lo; e < hi; e++) dst[e - lo] = g.col[e];
+    __shared__ int q_lo[kBlock], q_len[kBlock], q_dst[kBlock];
+    __shared__ int nq;
+    const int tid = threadIdx.x, lane = lane_id(), wib = tid / kWave;
+    for (int base = blockIdx.x * kBlock; base < g.n; base += gridDim.x * kBlock) {
+        if (tid == 0) nq = 0;
+        __syncthreads();
+        const int v = base + tid;
+        if (v < g.n) {
+            const int beg = g.row_ptr[v], end = g.row_ptr[v + 1];
+            const int lo = row_lower_bound(g.col, beg, end, (long long)s * N);
+            const int hi = row_lower_bound(g.col, lo, end, (long long)(s + 1) * N);
+            if (hi - lo < kWave) {
+                int32_t *dst = col_s + rp_s[v];
+                for (int e = lo; e < hi; e++) dst[e - lo] = g.col[e];
+            } else {
+                const int k = atomicAdd(&nq, 1);
+                q_lo[k] = lo;
+                q_len[k] = hi - lo;
+                q_dst[k] = rp_s[v];
+            }
+        }
+        __syncthreads();
+        for (int k = wib; k < nq; k += kBlock / kWave)
+            for (int i = lane; i < q_len[k]; i += kWave) col_s[q_dst[k] + i] = g.col[q_lo[k] + i];
+        __syncthreads();
     }
 }
 
@@ -437,6 +458,30 @@ static PullBlocked &pull_layout(Ctx &c, Graph &G, int N) {
 }
 
 void ensure_coo(Ctx &c, Graph &G);
+
+double pull_layout_prepare(Graph &G, int32_t seg_vertices, hipStream_t stream) {
+    Ctx c;
+    c.s = stream;
+    c.num_cus = G.num_cus;
+    const int N = seg_vertices;
+    const int S = (int)std::max<long long>(1, ((long long)G.n + N - 1) / N);
+    {
+        std::lock_guard<std::mutex> lk(G.mu);
+        if (G.pull_eb.count(S == 1 ? 0 : N)) return 0.0;
+    }
+    hipEvent_t e0, e1;
+    GG_HIP(hipEventCreate(&e0));
+    GG_HIP(hipEventCreate(&e1));
+    GG_HIP(hipEventRecord(e0, c.s));
+    pull_layout(c, G, N);
+    GG_HIP(hipEventRecord(e1, c.s));
+    GG_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    GG_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms;
+}
 
 void pr_run(Graph &G, const gg_schedule &sch, float damping, int iters, uint32_t flags, float *rank,
             hipStream_t stream, gg_stats *st) {

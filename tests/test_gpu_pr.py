@@ -83,6 +83,21 @@ def test_edgeblock_layout_matches_oracle(N, name):
     assert np.array_equal(seg, eseg)
 
 
+@pytest.mark.parametrize("name", ["rmat14", "star5000", "path100k"])
+def test_prepare_pull_blocking_then_pagerank(name):
+    h = host_graph(name)
+    G = gg.Graph.from_graphgen(h)  # a fresh graph: nothing cached yet
+    N = 777
+    ms = G.prepare_pull_blocking(N)
+    assert ms >= 0.0
+    assert G.prepare_pull_blocking(N) == 0.0  # cached
+    r = G.pagerank(gg.make_schedule(lb="strict", direction=gg.PULL, edge_blocking=True, blocking_size=N))
+    check_pr(r.cpu().numpy(), oracle_pr(name))
+    with pytest.raises(gg.GGError):
+        G.prepare_pull_blocking(0)
+    G.close()
+
+
 def test_pr_schedule_errors():
     G = dev_graph("rmat12")
     for kw in [dict(lb="cm", direction=gg.PULL), dict(lb="vp", direction=gg.PUSH),
