@@ -9,7 +9,7 @@ tuned schedule. `value` is the aggregate GTEPS of the step: traversed edges
 (BFS/SSSP/BC: sum of degrees of reached vertices; CC: m; PR: 20 m) over the
 step's wall time with the graph already in HBM.
 
-Prints ONE JSON line (rank 0). `--gpus N` with N > 1 is refused: this build
+Prints ONE JSON line (rank 0). `--gpus N` with N > 1 is refused: the library
 runs on one GPU.
 """
 from __future__ import annotations
@@ -152,7 +152,7 @@ def sweep_schedules(gg):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d" % args.gpus,
+        print("bench.py runs on one GPU only (the library has no multi-GPU path); got --gpus %d" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
