@@ -519,8 +519,11 @@ def batched_section(gg, graphgen, torch):
             ts.append(time.perf_counter() - t1)
         return sorted(ts)[len(ts) // 2]
 
-    d_multi = G.bfs_multi(bfs_src, sb)
-    s_multi, dl_multi = G.bc_multi(bc_src)
+    # one persistent launch per batch (fused PULL): 64 BFS sources, then the 16 BC sources
+    mb = gg.make_schedule(direction=gg.PULL, fusion=True)
+    mc = gg.make_schedule(fusion=True)
+    d_multi = G.bfs_multi(bfs_src, mb)
+    s_multi, dl_multi = G.bc_multi(bc_src, mc)
     ok = True
     for i in range(0, 64, 9):
         ok &= bool(torch.equal(d_multi[i], G.bfs(int(bfs_src[i]), sb)))
@@ -528,18 +531,23 @@ def batched_section(gg, graphgen, torch):
         s1, d1 = G.bc(int(bc_src[i]), sc)
         ok &= bool(torch.equal(s_multi[i], s1)) and bool(torch.equal(dl_multi[i].view(torch.int32),
                                                                         d1.view(torch.int32)))
-    t_multi = timed(lambda: (G.bfs_multi(bfs_src, sb), G.bc_multi(bc_src)))
+    t_multi = timed(lambda: (G.bfs_multi(bfs_src, mb), G.bc_multi(bc_src, mc)))
+    # the same batches with one launch per level (host-driven loop)
+    mb_l, mc_l = gg.make_schedule(direction=gg.PULL), gg.make_schedule()
+    t_levels = timed(lambda: (G.bfs_multi(bfs_src, mb_l), G.bc_multi(bc_src, mc_l)))
     t_single = timed(lambda: ([G.bfs(int(x), sb) for x in bfs_src], [G.bc(int(x), sc) for x in bc_src]), reps=1)
     reach = d_multi.cpu().numpy() >= 0
     edges = float(sum(deg[reach[i]].sum() for i in range(64)))
     reach_bc = s_multi.cpu().numpy() != 0
     edges += float(sum(deg[reach_bc[i]].sum() for i in range(16)))
-    log("batched: multi %.2f ms, single %.2f ms, speedup %.2fx, identical=%s" %
-        (t_multi * 1e3, t_single * 1e3, t_single / t_multi, ok))
+    t_best = min(t_multi, t_levels)
+    log("batched: persistent %.2f ms, launch per level %.2f ms, single %.2f ms, speedup %.2fx, identical=%s" %
+        (t_multi * 1e3, t_levels * 1e3, t_single * 1e3, t_single / t_best, ok))
     out = {"workload": "rmat20: 64 BFS + 16 BC sources (uniform over non-isolated vertices, seed 7)",
-           "ms_batched": round(t_multi * 1e3, 3), "ms_single_calls": round(t_single * 1e3, 3),
-           "speedup": round(t_single / t_multi, 2), "gteps_batched": round(edges / t_multi / 1e9, 2),
-           "queries_per_s": round(80 / t_multi, 1), "bit_identical": ok}
+           "ms_batched": round(t_best * 1e3, 3), "ms_batched_persistent": round(t_multi * 1e3, 3),
+           "ms_batched_launch_per_level": round(t_levels * 1e3, 3), "ms_single_calls": round(t_single * 1e3, 3),
+           "speedup": round(t_single / t_best, 2), "gteps_batched": round(edges / t_best / 1e9, 2),
+           "queries_per_s": round(80 / t_best, 1), "bit_identical": ok}
     # 64 SSSP sources: on R-MAT 20 and on the 2048^2 grid, each form with its
     # fastest delta (batched 64 / single STRICT 4096 on R-MAT; 4096 for both on
     # the grid), against single calls (on the grid 4 single calls stand for the 64)

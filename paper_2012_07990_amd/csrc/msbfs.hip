@@ -19,6 +19,7 @@
 #include "algos.hpp"
 #include "bc.hpp"
 #include "driver.hpp"
+#include "fused.hpp"
 #include "ms.hpp"
 
 namespace gg {
@@ -63,13 +64,13 @@ __device__ __forceinline__ void ms_record(int32_t *depth_vm, int K, int v, u64 n
 }
 
 // ---- multi-source BFS level (PULL with early exit once every missing source is found)
-__global__ __launch_bounds__(kBlock) void k_msbfs_pull(DevGraph g, int K, u64 all, u64 *visited, const u64 *front,
-                                                       u64 *next, int32_t *depth_vm, int level, int32_t *any) {
+__device__ __forceinline__ void msbfs_level(const DevGraph &g, int K, u64 all, u64 *visited, const u64 *front,
+                                            u64 *next, int32_t *depth_vm, int level, int32_t *any, Tid t) {
     __shared__ int q_v[kBlock];
     __shared__ int q_n;
     const int tid = threadIdx.x, lane = lane_id(), wib = tid / kWave;
     bool found_any = false;
-    for (int base = blockIdx.x * kBlock; base < g.n; base += gridDim.x * kBlock) {
+    for (int base = t.block * kBlock; base < g.n; base += t.nblocks * kBlock) {
         if (tid == 0) q_n = 0;
         __syncthreads();
         const int v = base + tid;
@@ -120,14 +121,14 @@ __global__ __launch_bounds__(kBlock) void k_msbfs_pull(DevGraph g, int K, u64 al
 // ---- multi-source BC forward level: new sources and their path counts -----------------
 constexpr int kBcGroup = 16;  // sources per BC pass (sigma / delta of a vertex: 128 B)
 
-__global__ __launch_bounds__(kBlock) void k_msbc_pull(DevGraph g, int K, u64 all, u64 *visited, const u64 *front,
-                                                      u64 *next, int32_t *depth_vm, u64 *sigma_vm, int level,
-                                                      int32_t *flags /* [0] any, [1] overflow */) {
+__device__ __forceinline__ void msbc_level(const DevGraph &g, int K, u64 all, u64 *visited, const u64 *front,
+                                           u64 *next, int32_t *depth_vm, u64 *sigma_vm, int level, int32_t *any,
+                                           int32_t *overflow, Tid t) {
     __shared__ int q_v[kBlock];
     __shared__ int q_n;
     const int tid = threadIdx.x, lane = lane_id(), wib = tid / kWave;
     bool found_any = false, wrap = false;
-    for (int base = blockIdx.x * kBlock; base < g.n; base += gridDim.x * kBlock) {
+    for (int base = t.block * kBlock; base < g.n; base += t.nblocks * kBlock) {
         if (tid == 0) q_n = 0;
         __syncthreads();
         const int v = base + tid;
@@ -210,20 +211,21 @@ __global__ __launch_bounds__(kBlock) void k_msbc_pull(DevGraph g, int K, u64 all
         }
         __syncthreads();
     }
-    if (__any(found_any) && lane_id() == 0) flags[0] = 1;
-    if (__any(wrap) && lane_id() == 0) flags[1] = 1;
+    if (__any(found_any) && lane_id() == 0) *any = 1;
+    if (__any(wrap) && lane_id() == 0) *overflow = 1;
 }
 
 // ---- multi-source BC backward level (same summation order as the single pass) -----------
-__global__ __launch_bounds__(kBlock) void k_msbc_backward(DevGraph g, int K, const int32_t *srcs, const int32_t *depth_vm,
-                                                          const u64 *sigma_vm, double *delta_vm, int level) {
+__device__ __forceinline__ void msbc_backward_level(const DevGraph &g, int K, const int32_t *srcs,
+                                                    const int32_t *depth_vm, const u64 *sigma_vm, double *delta_vm,
+                                                    int level, Tid t) {
     __shared__ int q_v[2][kBlock];
     __shared__ int q_n[2];
     __shared__ double s_w[kBcGroup][kBlock / kWave];
     __shared__ int s_src[kBcGroup];
     const int tid = threadIdx.x, lane = lane_id(), wib = tid / kWave;
     if (tid < kBcGroup) s_src[tid] = tid < K ? srcs[tid] : -1;
-    for (int base = blockIdx.x * kBlock; base < g.n; base += gridDim.x * kBlock) {
+    for (int base = t.block * kBlock; base < g.n; base += t.nblocks * kBlock) {
         if (tid < 2) q_n[tid] = 0;
         __syncthreads();
         const int v = base + tid;
@@ -322,6 +324,67 @@ __global__ __launch_bounds__(kBlock) void k_msbc_backward(DevGraph g, int K, con
     }
 }
 
+// ---- one launch per level (unfused schedules) ---------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_msbfs_pull(DevGraph g, int K, u64 all, u64 *visited, const u64 *front,
+                                                       u64 *next, int32_t *depth_vm, int level, int32_t *any) {
+    msbfs_level(g, K, all, visited, front, next, depth_vm, level, any, Tid::here());
+}
+__global__ __launch_bounds__(kBlock) void k_msbc_pull(DevGraph g, int K, u64 all, u64 *visited, const u64 *front,
+                                                      u64 *next, int32_t *depth_vm, u64 *sigma_vm, int level,
+                                                      int32_t *flags /* [0] any, [1] overflow */) {
+    msbc_level(g, K, all, visited, front, next, depth_vm, sigma_vm, level, flags, flags + 1, Tid::here());
+}
+__global__ __launch_bounds__(kBlock) void k_msbc_backward(DevGraph g, int K, const int32_t *srcs,
+                                                          const int32_t *depth_vm, const u64 *sigma_vm,
+                                                          double *delta_vm, int level) {
+    msbc_backward_level(g, K, srcs, depth_vm, sigma_vm, delta_vm, level, Tid::here());
+}
+
+// ---- one persistent launch per batch (fused schedules): levels separated by grid barriers --
+// flags: [0..2] "some vertex found a new source" per level (rotating), [3] path
+// count overflow, [4] levels run
+struct MsPullArgs {
+    DevGraph g;
+    int K;
+    u64 all;
+    u64 *visited, *f0, *f1;
+    int32_t *depth_vm;
+    u64 *sigma_vm;      // BC only
+    double *delta_vm;   // BC only
+    const int32_t *srcs;
+    int32_t *flags;
+    GridBarrier bar;
+};
+
+template <bool BC>
+__global__ __launch_bounds__(kBlock) void k_ms_pull_fused(MsPullArgs a) {
+    const Tid t = Tid::here();
+    GridBarrier bar = a.bar;
+    const bool lead = t.block == 0 && threadIdx.x == 0;
+    int level = 1;
+    bool ok = true;
+    for (;; level++) {
+        const u64 *front = (level & 1) ? a.f0 : a.f1;
+        u64 *next = (level & 1) ? a.f1 : a.f0;
+        int32_t *any = a.flags + level % 3;
+        if (lead) __hip_atomic_store(a.flags + (level + 1) % 3, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if constexpr (BC)
+            msbc_level(a.g, a.K, a.all, a.visited, front, next, a.depth_vm, a.sigma_vm, level, any, a.flags + 3, t);
+        else
+            msbfs_level(a.g, a.K, a.all, a.visited, front, next, a.depth_vm, level, any, t);
+        if (!grid_sync(bar)) { ok = false; break; }
+        if (load_relaxed(any) == 0) break;
+    }
+    // levels 0 .. level-1 hold vertices
+    if constexpr (BC) {
+        for (int L = level - 2; ok && L >= 0; L--) {
+            msbc_backward_level(a.g, a.K, a.srcs, a.depth_vm, a.sigma_vm, a.delta_vm, L, t);
+            if (!grid_sync(bar)) ok = false;
+        }
+    }
+    if (lead) a.flags[4] = level;
+}
+
 struct MsBuffers {
     u64 *visited, *front, *next;
     int32_t *depth_vm;
@@ -333,6 +396,25 @@ static MsBuffers ms_buffers(Workspace &ws, int n, int K) {
     ws.aux_u64[2].ensure(n);
     ws.aux_i32[3].ensure((size_t)n * (K > 0 ? K : 1));
     return MsBuffers{ws.aux_u64[0].p, ws.aux_u64[1].p, ws.aux_u64[2].p, ws.aux_i32[3].p};
+}
+
+// The batch's levels (and, for BC, its backward levels) in one persistent
+// launch; returns the number of levels run. Flags land in ws.h_i32[0..7].
+template <bool BC>
+static int ms_pull_persistent(Ctx &c, Graph &G, Workspace &ws, int K, u64 all, const MsBuffers &b, u64 *sig,
+                              double *del, const int32_t *srcs) {
+    const void *kern = (const void *)k_ms_pull_fused<BC>;
+    // every level sweeps all vertices: many waves per compute unit hide the
+    // gathers' latency, at a barrier cost that grows with the workgroups
+    const int blocks = fused_grid(kern, 4, c.num_cus);
+    MsPullArgs a{G.view(), K, all, b.visited, b.front, b.next, b.depth_vm, sig, del, srcs, ws.counters.p,
+                 prepare_barrier(c, ws, blocks)};
+    void *args[] = {&a};
+    launch_cooperative(c, kern, blocks, args);
+    check_barrier(c, ws);
+    GG_HIP(hipMemcpyAsync(ws.h_i32.p, ws.counters.p, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
+    GG_HIP(hipStreamSynchronize(c.s));
+    return ws.h_i32.p[4];
 }
 
 void msbfs_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &sch, int32_t *depth, hipStream_t stream,
@@ -362,15 +444,21 @@ void msbfs_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &sch, int
     GG_CHECK_LAUNCH();
     c.launches++;
     const u64 all = k == 64 ? ~0ull : ((1ull << k) - 1);
-    for (int level = 1;; level++) {
-        fill_i32(c, ws->counters.p, 1, 0);
-        hipLaunchKernelGGL(k_msbfs_pull, dim3(blocks_for(n, kBlock, 16384)), dim3(kBlock), 0, c.s, g, k, all, b.visited,
-                           b.front, b.next, b.depth_vm, level, ws->counters.p);
-        GG_CHECK_LAUNCH();
-        c.launches++;
-        std::swap(b.front, b.next);
-        if (st) { st->iterations++; st->pull_iterations++; }
-        if (read_i32(c, ws->counters.p, ws->h_i32.p) == 0) break;
+    if (sch.s1.kernel_fusion) {
+        fill_i32(c, ws->counters.p, 8, 0);
+        const int levels = ms_pull_persistent<false>(c, G, *ws, k, all, b, nullptr, nullptr, nullptr);
+        if (st) { st->iterations = levels; st->pull_iterations = levels; st->fused = 1; }
+    } else {
+        for (int level = 1;; level++) {
+            fill_i32(c, ws->counters.p, 1, 0);
+            hipLaunchKernelGGL(k_msbfs_pull, dim3(blocks_for(n, kBlock, 16384)), dim3(kBlock), 0, c.s, g, k, all,
+                               b.visited, b.front, b.next, b.depth_vm, level, ws->counters.p);
+            GG_CHECK_LAUNCH();
+            c.launches++;
+            std::swap(b.front, b.next);
+            if (st) { st->iterations++; st->pull_iterations++; }
+            if (read_i32(c, ws->counters.p, ws->h_i32.p) == 0) break;
+        }
     }
     hipLaunchKernelGGL((k_ms_transpose<int32_t, int32_t>), dim3(blocks_for(n, 64, 16384)), dim3(kBlock), 0, c.s,
                        b.depth_vm, n, k, depth, 0);
@@ -380,7 +468,7 @@ void msbfs_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &sch, int
     scope.finish();
 }
 
-void msbc_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &, uint64_t *sigma_out, float *delta_out,
+void msbc_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &sch, uint64_t *sigma_out, float *delta_out,
               hipStream_t stream, gg_stats *st) {
     Ctx c;
     c.s = stream;
@@ -408,26 +496,33 @@ void msbc_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &, uint64_
         GG_CHECK_LAUNCH();
         c.launches++;
         const u64 all = (1ull << K) - 1;
-        int levels = 1;  // levels present: 0 .. levels-1
-        for (int level = 1;; level++) {
-            fill_i32(c, ws->counters.p, 2, 0);
-            hipLaunchKernelGGL(k_msbc_pull, dim3(blocks_for(n, kBlock, 16384)), dim3(kBlock), 0, c.s, g, K, all,
-                               b.visited, b.front, b.next, b.depth_vm, sig.p, level, ws->counters.p);
-            GG_CHECK_LAUNCH();
-            c.launches++;
-            std::swap(b.front, b.next);
-            if (st) { st->iterations++; st->pull_iterations++; }
-            GG_HIP(hipMemcpyAsync(ws->h_i32.p, ws->counters.p, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
-            GG_HIP(hipStreamSynchronize(c.s));
-            require(ws->h_i32.p[1] == 0, GG_ERR_OVERFLOW, "a shortest-path count exceeds 2^64-1");
-            if (ws->h_i32.p[0] == 0) break;
-            levels = level + 1;
-        }
-        for (int level = levels - 2; level >= 0; level--) {
-            hipLaunchKernelGGL(k_msbc_backward, dim3(blocks_for(n, kBlock, 16384)), dim3(kBlock), 0, c.s, g, K,
-                               dsrc.p + j0, b.depth_vm, sig.p, del.p, level);
-            GG_CHECK_LAUNCH();
-            c.launches++;
+        if (sch.s1.kernel_fusion) {
+            fill_i32(c, ws->counters.p, 8, 0);
+            const int levels = ms_pull_persistent<true>(c, G, *ws, K, all, b, sig.p, del.p, dsrc.p + j0);
+            if (st) { st->iterations += levels; st->pull_iterations += levels; st->fused = 1; }
+            require(ws->h_i32.p[3] == 0, GG_ERR_OVERFLOW, "a shortest-path count exceeds 2^64-1");
+        } else {
+            int levels = 1;  // levels present: 0 .. levels-1
+            for (int level = 1;; level++) {
+                fill_i32(c, ws->counters.p, 2, 0);
+                hipLaunchKernelGGL(k_msbc_pull, dim3(blocks_for(n, kBlock, 16384)), dim3(kBlock), 0, c.s, g, K, all,
+                                   b.visited, b.front, b.next, b.depth_vm, sig.p, level, ws->counters.p);
+                GG_CHECK_LAUNCH();
+                c.launches++;
+                std::swap(b.front, b.next);
+                if (st) { st->iterations++; st->pull_iterations++; }
+                GG_HIP(hipMemcpyAsync(ws->h_i32.p, ws->counters.p, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
+                GG_HIP(hipStreamSynchronize(c.s));
+                require(ws->h_i32.p[1] == 0, GG_ERR_OVERFLOW, "a shortest-path count exceeds 2^64-1");
+                if (ws->h_i32.p[0] == 0) break;
+                levels = level + 1;
+            }
+            for (int level = levels - 2; level >= 0; level--) {
+                hipLaunchKernelGGL(k_msbc_backward, dim3(blocks_for(n, kBlock, 16384)), dim3(kBlock), 0, c.s, g, K,
+                                   dsrc.p + j0, b.depth_vm, sig.p, del.p, level);
+                GG_CHECK_LAUNCH();
+                c.launches++;
+            }
         }
         hipLaunchKernelGGL((k_ms_transpose<u64, u64>), dim3(blocks_for(n, 64, 16384)), dim3(kBlock), 0, c.s, sig.p, n,
                            K, reinterpret_cast<u64 *>(sigma_out), j0);

@@ -87,7 +87,8 @@ struct GpuExecutor : serve::Executor {
         // push loops (SSSP always; BFS under a plain PUSH schedule)
         const bool ms_push = b.algo == GG_ALGO_SSSP || (b.algo == GG_ALGO_BFS && !s.hybrid && s.s1.direction == GG_PUSH);
         const bool batched = k > 1 || (ms_push && G.m < 8ll * G.n);
-        const bool fused = batched ? ms_push : s.s1.kernel_fusion;
+        // persistent: the push loops, and the pull forms under a fused schedule
+        const bool fused = (batched && ms_push) || s.s1.kernel_fusion;
         std::shared_lock<std::shared_mutex> shared(device, std::defer_lock);
         std::unique_lock<std::shared_mutex> exclusive(device, std::defer_lock);
         if (fused) exclusive.lock();

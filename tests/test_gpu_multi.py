@@ -24,6 +24,8 @@ def _ms_sched(form):
         return gg.make_schedule()
     if form == "pull":
         return gg.make_schedule(direction=gg.PULL)
+    if form == "pull_fused":
+        return gg.make_schedule(direction=gg.PULL, fusion=True)
     s = gg.schedule_preset(gg.ALGO_BFS, gg.PRESET_POWERLAW)
     s.threshold = 0.01
     return s
@@ -32,14 +34,14 @@ def _ms_sched(form):
 @pytest.mark.parametrize("name", ["rmat12", "rmat14", "grid64", "star5000", "cliques", "isolated7", "single",
                                   "path100k"])
 @pytest.mark.parametrize("k", [1, 7, 64])
-@pytest.mark.parametrize("form", ["push", "pull", "hybrid"])
+@pytest.mark.parametrize("form", ["push", "pull", "hybrid", "pull_fused"])
 def test_bfs_multi_matches_single_and_oracle(name, k, form):
     G = dev_graph(name)
     srcs = _sources(name, k)
     st = gg.Stats()
     d = G.bfs_multi(srcs, _ms_sched(form), stats=st).cpu().numpy()
     assert d.shape == (k, host_graph(name).n)
-    assert st.fused == (1 if form == "push" else 0)
+    assert st.fused == (1 if form in ("push", "pull_fused") else 0)
     for i, s in enumerate(srcs):
         assert_int_equal(d[i], oracle_bfs(name, int(s)), "bfs_multi row %d" % i)
     single = G.bfs(int(srcs[0]), gg.make_schedule(lb="etwc")).cpu().numpy()
@@ -59,10 +61,13 @@ def test_bfs_multi_duplicate_sources(form):
 @pytest.mark.parametrize("name", ["rmat12", "rmat14", "star5000", "cliques", "isolated7", "single", "fullgrid34",
                                   "path100k"])
 @pytest.mark.parametrize("k", [1, 5, 16, 20])
-def test_bc_multi_bit_identical_to_single(name, k):
+@pytest.mark.parametrize("fused", [False, True])
+def test_bc_multi_bit_identical_to_single(name, k, fused):
     G = dev_graph(name)
     srcs = _sources(name, k, seed=11)
-    sig, dl = G.bc_multi(srcs)
+    st = gg.Stats()
+    sig, dl = G.bc_multi(srcs, gg.make_schedule(fusion=fused), stats=st)
+    assert st.fused == (1 if fused else 0)
     sig = sig.cpu().numpy().view(np.uint64)
     dl = dl.cpu().numpy()
     for i, s in enumerate(srcs):
@@ -133,9 +138,10 @@ def test_multi_argument_errors():
     assert e.value.status in (gg.ERR_INVALID_ARG, gg.ERR_UNSUPPORTED_SCHEDULE)
 
 
-def test_bc_multi_overflow():
+@pytest.mark.parametrize("fused", [False, True])
+def test_bc_multi_overflow(fused):
     g = graphgen.full_grid(35, 35)
     G = gg.Graph.from_csr(g.n, g.row_ptr, g.col)
     with pytest.raises(gg.GGError) as e:
-        G.bc_multi([0, 1])
+        G.bc_multi([0, 1], gg.make_schedule(fusion=fused))
     assert e.value.status == gg.ERR_OVERFLOW
