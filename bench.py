@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, GB/s
 PR_SEGMENT = 1 << 20   # PageRank pull EdgeBlocking: source segments of 2^20 vertices
+PR_LDS_SOURCES = 8192  # highest-degree sources per segment the STRICT kernel keeps in LDS
 
 
 def measured_traffic(kernel_src: str, summary: str, schedule_tag: str):
@@ -332,12 +333,20 @@ def main():
         alg_bytes = (8.0 * m + 16.0 * pairs) / launches_per_round
         achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9
         traffic = measured_traffic("paper_2012_07990_amd/csrc/pr.hip", "k_pr_strict_chunks_rmat22.md",
-                                   "PULL+STRICT+EB(%d)" % PR_SEGMENT)
+                                   "PULL+STRICT+EB(%d)+LDS(%d)" % (PR_SEGMENT, PR_LDS_SOURCES))
+        # the same rounds with every source gathered from global memory
+        st0 = gg.Stats()
+        st0.flags = gg.STATS_TIME_KERNELS
+        G.pagerank(scheds["pr"], iters=20, stats=st0, lds_cache=False)
+        torch.cuda.synchronize()
+        plain_ms = st0.kernel_ms / max(st0.kernel_launches, 1)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "kernel": st.kernel_name.decode() if isinstance(st.kernel_name, bytes) else str(st.kernel_name),
                 "per_launch_ms": round(per_launch_ms, 5), "bytes_per_launch": round(alg_bytes),
-                "launches_per_round": launches_per_round, "row_segment_pairs": pairs}
+                "launches_per_round": launches_per_round, "row_segment_pairs": pairs,
+                "lds_cached_sources_per_segment": PR_LDS_SOURCES,
+                "per_launch_ms_without_lds_cache": round(plain_ms, 5)}
 
     tuned = tune_section(gg, G, scheds, run, src, edges, torch, args) if args.tune else None
 

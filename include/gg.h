@@ -219,6 +219,10 @@ gg_status gg_cc(gg_graph *g, const gg_schedule *s, int32_t *label_dev, gg_stream
                 gg_stats *stats);
 
 #define GG_PR_NO_DANGLING 1u /* drop the mass of zero-degree vertices */
+/* PULL STRICT only: gather every source's contribution from global memory
+   instead of keeping the highest-degree sources of each segment in LDS.
+   The results are bit-identical either way (same values, same order). */
+#define GG_PR_NO_LDS_CACHE 2u
 /* PageRank, fp32: `iters` power-iteration rounds from 1/n with damping
    `damping`; zero-degree mass spread uniformly unless GG_PR_NO_DANGLING.
    rank_dev[n] float. Requires GG_SYMMETRIC. */

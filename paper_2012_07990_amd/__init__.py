@@ -47,6 +47,7 @@ DEDUP_MONOTONIC_COUNTERS, DEDUP_BITMAP, DEDUP_BOOLMAP = 0, 1, 2
 PRESET_DEFAULT, PRESET_BFS_HYBRID, PRESET_ROAD_FUSED, PRESET_POWERLAW = 0, 1, 2, 3
 INPUT_DEVICE, VALIDATE, SYMMETRIC = 1, 2, 4
 PR_NO_DANGLING = 1
+PR_NO_LDS_CACHE = 2
 STATS_COUNT_EDGES = 1
 STATS_TIME_KERNELS = 2
 INT32_MAX = 2**31 - 1
@@ -363,10 +364,12 @@ class Graph:
         gg_cc(self, sched, out, stats=stats)
         return out
 
-    def pagerank(self, sched=None, damping=0.85, iters=20, dangling=True, stats=None, out=None):
+    def pagerank(self, sched=None, damping=0.85, iters=20, dangling=True, stats=None, out=None,
+                 lds_cache=True):
         torch = _torch()
         out = self._empty(self.n, torch.float32) if out is None else out
-        gg_pagerank(self, sched, damping, iters, 0 if dangling else PR_NO_DANGLING, out, stats=stats)
+        flags = (0 if dangling else PR_NO_DANGLING) | (0 if lds_cache else PR_NO_LDS_CACHE)
+        gg_pagerank(self, sched, damping, iters, flags, out, stats=stats)
         return out
 
     def bc(self, src, sched=None, stats=None):

@@ -285,6 +285,8 @@ gg_status gg_pagerank(gg_graph *g, const gg_schedule *s, float damping, int32_t 
         check_graph(g);
         require(rank_dev != nullptr, GG_ERR_INVALID_ARG, "rank is NULL");
         require(iters >= 0, GG_ERR_INVALID_ARG, "iters must be >= 0");
+        require((flags & ~(GG_PR_NO_DANGLING | GG_PR_NO_LDS_CACHE)) == 0, GG_ERR_INVALID_ARG,
+                "unknown PageRank flags");
         require(damping >= 0.f && damping <= 1.f, GG_ERR_INVALID_ARG, "damping must be in [0, 1]");
         require(g->g.symmetric, GG_ERR_INVALID_ARG, "PageRank needs a symmetric graph (GG_SYMMETRIC)");
         const gg_schedule sc = s ? *s : default_schedule();

@@ -123,6 +123,7 @@ struct Workspace {
     DevBuf<double> aux_f64[2];
     DevBuf<uint8_t> member;               // EDGE_ONLY input-frontier membership map
     DevBuf<float> pr_contrib[2];  // PageRank
+    DevBuf<float> pr_hot[2];      // PageRank STRICT: contributions of the LDS-cached sources
     DevBuf<double> pr_acc, pr_head, pr_tail;
     DevBuf<double> pr_partial, pr_dangling;
     DevBuf<unsigned long long> ms_sigma;  // multi-source BC path counts (vertex-major)
@@ -150,6 +151,9 @@ struct PullBlocked {
     std::vector<long long> m_s, col_base;
     DevBuf<int32_t> chunk_rows;            // per segment: owner rows of each chunk's first/last edge
     std::vector<long long> chunk_base, nchunks;
+    int hot_k = 0;                         // sources per segment cached in LDS (slots per segment)
+    DevBuf<int32_t> hot_slot;              // n: segment*hot_k + slot of a cached source, else -1
+    DevBuf<int32_t> hcol;                  // col_ptr's layout with cached sources as ~slot
 };
 
 struct Graph {

@@ -14,7 +14,13 @@
 //                      separated by barriers, so the order is fixed)
 //   PULL STRICT        every workgroup takes the same number of edges; rows
 //                      that cross a chunk boundary are completed from the
-//                      chunks' head/tail partial sums in the vertex apply
+//                      chunks' head/tail partial sums in the vertex apply.
+//                      Each workgroup keeps a copy of the contributions of
+//                      the segment's kPrHotK highest-degree sources in LDS
+//                      (refreshed by the vertex apply every round): edges
+//                      from those sources read LDS instead of issuing a
+//                      random 4-byte global gather (the same values in the
+//                      same order, so the sums are unchanged)
 //   PUSH EDGE_ONLY     every edge adds contrib(src) to acc(dst) atomically
 //   PUSH EDGE_ONLY+EB  the same over the EdgeBlocked COO, one launch per
 //                      destination segment (the edge processing algorithm)
@@ -30,7 +36,10 @@
 
 namespace gg {
 
-constexpr int kPrChunk = kBlock * 8;  // STRICT: edges per workgroup
+constexpr int kPrChunk = kWave * 8;   // STRICT: edges per chunk (one wavefront's)
+constexpr int kPrWaves = 16;          // STRICT: wavefronts per workgroup
+constexpr int kPrHotK = 8192;         // STRICT: highest-degree sources per segment cached in LDS
+constexpr int kHotBins = 4096;        // degree histogram bins (the last one collects the rest)
 
 struct PrArgs {
     DevGraph g;
@@ -43,6 +52,8 @@ struct PrArgs {
     double *partials;       // per-block dangling partial sums (reduced by k_pr_dangling)
     int dangling;           // 0: drop the dangling mass
     double *acc;            // STRICT / PUSH accumulators (reset after read)
+    const int32_t *hot_slot;  // STRICT LDS cache: slot of each cached source (-1: not cached)
+    float *hot_out;           // the cached sources' contributions, by slot
 };
 
 __device__ __forceinline__ double pr_base(const PrArgs &a) {
@@ -53,7 +64,12 @@ __device__ __forceinline__ double pr_base(const PrArgs &a) {
 __device__ __forceinline__ void pr_apply(const PrArgs &a, int v, double base, double acc, int deg, double &dl) {
     const float nv = (float)(base + (double)a.damping * acc);
     if (a.rank_out) a.rank_out[v] = nv;
-    a.contrib_out[v] = deg > 0 ? nv / (float)deg : 0.f;
+    const float cv = deg > 0 ? nv / (float)deg : 0.f;
+    a.contrib_out[v] = cv;
+    if (a.hot_slot) {
+        const int sl = a.hot_slot[v];
+        if (sl >= 0) a.hot_out[sl] = cv;
+    }
     if (deg == 0) dl += (double)nv;
 }
 
@@ -94,7 +110,12 @@ __global__ __launch_bounds__(kBlock) void k_pr_init(PrArgs a) {
     for (int v = blockIdx.x * kBlock + threadIdx.x; v < a.g.n; v += gridDim.x * kBlock) {
         const int deg = a.g.row_ptr[v + 1] - a.g.row_ptr[v];
         if (a.rank_out) a.rank_out[v] = r0;
-        a.contrib_out[v] = deg > 0 ? r0 / (float)deg : 0.f;
+        const float cv = deg > 0 ? r0 / (float)deg : 0.f;
+        a.contrib_out[v] = cv;
+        if (a.hot_slot) {
+            const int sl = a.hot_slot[v];
+            if (sl >= 0) a.hot_out[sl] = cv;
+        }
         if (deg == 0) dl += (double)r0;
         if (a.acc) a.acc[v] = 0.0;
     }
@@ -225,76 +246,109 @@ __global__ __launch_bounds__(kBlock) void k_pr_partition(const int32_t *rp, int 
     }
 }
 
-// STRICT: chunk c holds edges [c*C, c*C + C) of a (segment) CSR. Rows
-// entirely inside a chunk add their sum to accum; the chunk's first and last
-// rows also leave their in-chunk partial sums in head[c] / tail[c], which
-// k_pr_fixup adds for the rows that span chunks.
-__global__ __launch_bounds__(kBlock) void k_pr_strict_chunks(const int32_t *rp, const int32_t *col, long long m,
-                                                             const float *contrib, const int32_t *chunk_rows,
-                                                             double *accum, double *head, double *tail,
-                                                             long long nchunks) {
-    __shared__ float vals[kPrChunk];
-    __shared__ int s_r0, s_r1;
-    __shared__ int long_r[kPrChunk / 32 + 1];
-    __shared__ int n_long;
-    const int tid = threadIdx.x, lane = lane_id(), wib = tid / kWave;
-    for (long long c = blockIdx.x; c < nchunks; c += gridDim.x) {
+// LDS writes of one wavefront made visible to its other lanes (no workgroup
+// barrier: the wavefronts of a workgroup run their chunks independently)
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// STRICT: chunk c holds edges [c*C, c*C + C) of a (segment) CSR and belongs to
+// one wavefront. Rows entirely inside a chunk add their sum to accum; the
+// chunk's first and last rows also leave their in-chunk partial sums in
+// head[c] / tail[c], which k_pr_fixup adds for the rows that span chunks.
+// With HK > 0 the column entries of cached sources hold ~slot and their values
+// come from the HK-entry LDS copy of `hot`, loaded once per workgroup (the
+// grid is sized to stay resident).
+template <int HK>
+__global__ __launch_bounds__(kWave *kPrWaves) __attribute__((amdgpu_waves_per_eu(8))) void k_pr_strict_chunks(
+    const int32_t *rp, const int32_t *col, long long m, const float *contrib, const float *hot,
+    const int32_t *chunk_rows, double *accum, double *head, double *tail, long long nchunks) {
+    __shared__ float vals[kPrWaves][kPrChunk];
+    __shared__ float4 hot_s4[HK > 0 ? HK / 4 : 1];
+    const float *hot_s = reinterpret_cast<const float *>(hot_s4);
+    const int lane = lane_id(), wib = (int)threadIdx.x / kWave;
+    if constexpr (HK > 0) {
+        const float4 *h4 = reinterpret_cast<const float4 *>(hot);
+        for (int i = threadIdx.x; i < HK / 4; i += kWave * kPrWaves) hot_s4[i] = h4[i];
+        __syncthreads();
+    }
+    float *cv = vals[wib];
+    for (long long c = (long long)blockIdx.x * kPrWaves + wib; c < nchunks; c += (long long)gridDim.x * kPrWaves) {
         const long long E0 = c * kPrChunk, E1 = (E0 + kPrChunk < m) ? E0 + kPrChunk : m;
         // all column loads, then all gathers, without branches in between (a
         // conditional per edge made the compiler wait for each load in turn);
-        // edges past the chunk's end re-read its last edge and are not stored
-        constexpr int kPer = kPrChunk / kBlock;
+        // edges past the chunk's end re-read its last edge and are not stored.
+        // The column stream is read once: non-temporal loads keep it from
+        // evicting the segment's contributions from L2
+        constexpr int kPer = kPrChunk / kWave;
         int cidx[kPer];
         float cval[kPer];
 #pragma unroll
         for (int k = 0; k < kPer; k++) {
-            const long long e = E0 + k * kBlock + tid;
-            cidx[k] = col[e < E1 ? e : E1 - 1];
+            const long long e = E0 + k * kWave + lane;
+            cidx[k] = __builtin_nontemporal_load(&col[e < E1 ? e : E1 - 1]);
         }
+        if constexpr (HK > 0) {
+            // a cached source's lane reads contrib[0] (one shared line for the
+            // wavefront) and takes the LDS value; the rest read LDS entry 0
+            float gv[kPer];
 #pragma unroll
-        for (int k = 0; k < kPer; k++) cval[k] = contrib[cidx[k]];
+            for (int k = 0; k < kPer; k++) gv[k] = contrib[cidx[k] >= 0 ? cidx[k] : 0];
+#pragma unroll
+            for (int k = 0; k < kPer; k++) {
+                const int i = cidx[k];
+                const float hv = hot_s[i >= 0 ? 0 : ~i];
+                cval[k] = i >= 0 ? gv[k] : hv;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kPer; k++) cval[k] = contrib[cidx[k]];
+        }
 #pragma unroll
         for (int k = 0; k < kPer; k++) {
-            const long long e = E0 + k * kBlock + tid;
-            if (e < E1) vals[e - E0] = cval[k];
+            const long long e = E0 + k * kWave + lane;
+            if (e < E1) cv[e - E0] = cval[k];
         }
-        if (tid == 0) {
-            s_r0 = chunk_rows[2 * c];
-            s_r1 = chunk_rows[2 * c + 1];
-            n_long = 0;
-        }
-        __syncthreads();
-        const int r0 = s_r0, r1 = s_r1;
-        // short rows (< 32 in-chunk edges): one lane each; long rows queued
-        for (int r = r0 + tid; r <= r1; r += kBlock) {
-            const long long rb = rp[r], re = rp[r + 1];
-            const int lo = (int)((rb > E0 ? rb : E0) - E0), hi = (int)((re < E1 ? re : E1) - E0);
-            if (hi - lo >= 32) {
-                const int k = atomicAdd(&n_long, 1);
-                long_r[k] = r;
-                continue;
+        const int r0 = chunk_rows[2 * c], r1 = chunk_rows[2 * c + 1];
+        wave_lds_sync();
+        // short rows (< 32 in-chunk edges): one lane each, in CSR order; long
+        // rows: the whole wavefront, lane-strided sums reduced by a butterfly
+        for (int rbase = r0; rbase <= r1; rbase += kWave) {
+            const int r = rbase + lane;
+            int lo = 0, hi = 0, whole = 0;
+            if (r <= r1) {
+                const long long rb = rp[r], re = rp[r + 1];
+                lo = (int)((rb > E0 ? rb : E0) - E0);
+                hi = (int)((re < E1 ? re : E1) - E0);
+                whole = rb >= E0 && re <= E1;
             }
-            double sum = 0.0;
-            for (int i = lo; i < hi; i++) sum += (double)vals[i];
-            if (rb >= E0 && re <= E1) { if (hi > lo) accum[r] += sum; }
-            if (r == r0) head[c] = sum;
-            if (r == r1) tail[c] = sum;
-        }
-        __syncthreads();
-        for (int k = wib; k < n_long; k += kBlock / kWave) {
-            const int r = long_r[k];
-            const long long rb = rp[r], re = rp[r + 1];
-            const int lo = (int)((rb > E0 ? rb : E0) - E0), hi = (int)((re < E1 ? re : E1) - E0);
-            double sum = 0.0;
-            for (int i = lo + lane; i < hi; i += kWave) sum += (double)vals[i];
-            sum = wave_sum(sum);
-            if (lane == 0) {
-                if (rb >= E0 && re <= E1) accum[r] += sum;
+            const bool lng = hi - lo >= 32;
+            if (r <= r1 && !lng) {
+                double sum = 0.0;
+                for (int i = lo; i < hi; i++) sum += (double)cv[i];
+                if (whole && hi > lo) accum[r] += sum;
                 if (r == r0) head[c] = sum;
                 if (r == r1) tail[c] = sum;
             }
+            uint64_t lm = __ballot(lng);
+            while (lm) {
+                const int o = first_lane(lm);
+                lm &= lm - 1;
+                const int rr = rbase + o, llo = __shfl(lo, o, kWave), lhi = __shfl(hi, o, kWave);
+                const int wh = __shfl(whole, o, kWave);
+                double sum = 0.0;
+                for (int i = llo + lane; i < lhi; i += kWave) sum += (double)cv[i];
+                sum = wave_sum(sum);
+                if (lane == 0) {
+                    if (wh) accum[rr] += sum;
+                    if (rr == r0) head[c] = sum;
+                    if (rr == r1) tail[c] = sum;
+                }
+            }
         }
-        __syncthreads();
+        wave_lds_sync();  // this chunk's reads of cv come before the next chunk's writes
     }
 }
 
@@ -392,6 +446,118 @@ __global__ __launch_bounds__(kBlock) void k_pr_push_edges(const int32_t *src, co
         atomic_add_f64(&acc[dst[e]], (double)contrib[src[e]]);
 }
 
+// ---- STRICT LDS cache of the highest-degree sources of each segment. On a
+// symmetric graph a source appears in as many pull rows as its degree, so the
+// kPrHotK highest-degree vertices of a segment cover the most gathers.
+constexpr int kHotSpan = 8192;  // vertices per workgroup in the histogram pass
+
+// per segment: hist[s][min(deg, kHotBins-1)] += 1 (small bins of the
+// workgroup's first segment counted in LDS first)
+__global__ __launch_bounds__(kBlock) void k_hot_hist(DevGraph g, int N, int32_t *hist) {
+    __shared__ int sh[kBlock];
+    const int tid = threadIdx.x;
+    const long long v0 = (long long)blockIdx.x * kHotSpan;
+    const long long v1 = v0 + kHotSpan < g.n ? v0 + kHotSpan : g.n;
+    const int s0 = (int)(v0 / N);
+    sh[tid] = 0;
+    __syncthreads();
+    for (long long v = v0 + tid; v < v1; v += kBlock) {
+        const int d = g.row_ptr[v + 1] - g.row_ptr[v];
+        const int b = d < kHotBins - 1 ? d : kHotBins - 1;
+        const int sg = (int)(v / N);
+        if (sg == s0 && b < kBlock) atomicAdd(&sh[b], 1);
+        else atomicAdd(&hist[(long long)sg * kHotBins + b], 1);
+    }
+    __syncthreads();
+    if (sh[tid]) atomicAdd(&hist[(long long)s0 * kHotBins + tid], sh[tid]);
+}
+
+// per segment: thr[s] = the smallest degree bin t >= 1 such that at most K
+// vertices have a bin >= t (the last bin alone may exceed K; slots then run
+// out and the rest stay uncached)
+__global__ __launch_bounds__(kBlock) void k_hot_threshold(const int32_t *hist, int K, int32_t *thr) {
+    constexpr int kPer = kHotBins / kBlock;
+    __shared__ int part[kBlock];
+    const int32_t *h = hist + (long long)blockIdx.x * kHotBins;
+    int t = 0;
+    for (int i = 0; i < kPer; i++) t += h[threadIdx.x * kPer + i];
+    part[threadIdx.x] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long acc = 0;
+        int th = 1;
+        for (int i = kBlock - 1; i >= 0 && th == 1; i--) {
+            if (acc + part[i] <= K) { acc += part[i]; continue; }
+            for (int b = i * kPer + kPer - 1; b >= i * kPer; b--) {
+                if (acc + h[b] > K) { th = b + 1 < kHotBins ? b + 1 : kHotBins - 1; break; }
+                acc += h[b];
+            }
+        }
+        thr[blockIdx.x] = th;
+    }
+}
+
+// pass 0: every vertex of bin >= thr gets a slot (while the segment has
+// slots), the others -1; pass 1: vertices of bin thr-1 fill the slots left
+__global__ __launch_bounds__(kBlock) void k_hot_assign(DevGraph g, int N, int K, const int32_t *thr, int pass,
+                                                       int32_t *nslot, int32_t *hot_slot) {
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < g.n; v += gridDim.x * kBlock) {
+        const int d = g.row_ptr[v + 1] - g.row_ptr[v];
+        const int b = d < kHotBins - 1 ? d : kHotBins - 1;
+        const int sg = v / N, t = thr[sg];
+        bool want;
+        if (pass == 0) {
+            want = b >= t;
+            if (!want) hot_slot[v] = -1;
+        } else {
+            want = t > 1 && b == t - 1;
+        }
+        if (!want) continue;
+        const int k = atomicAdd(&nslot[sg], 1);
+        if (k < K) hot_slot[v] = sg * K + k;
+        else if (pass == 0) hot_slot[v] = -1;
+    }
+}
+
+// the pull columns with every cached source u replaced by ~(its slot within
+// u's segment)
+__global__ __launch_bounds__(kBlock) void k_hot_encode(const int32_t *col, long long m, int N, int K,
+                                                       const int32_t *hot_slot, int32_t *hcol) {
+    for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < m; e += (long long)gridDim.x * kBlock) {
+        const int u = col[e];
+        const int sl = hot_slot[u];
+        hcol[e] = sl >= 0 ? ~(sl - (u / N) * K) : u;
+    }
+}
+
+static void build_hot_cache(Ctx &c, const DevGraph &g, PullBlocked &pb) {
+    const int n = g.n, S = pb.S, N = pb.S == 1 ? std::max(n, 1) : pb.N;
+    DevBuf<int32_t> hist, thr, nslot;
+    hist.ensure((size_t)S * kHotBins);
+    thr.ensure(S);
+    nslot.ensure(S);
+    fill_i32(c, hist.p, (long long)S * kHotBins, 0);
+    fill_i32(c, nslot.p, S, 0);
+    pb.hot_slot.ensure(std::max(n, 1));
+    pb.hcol.ensure((size_t)std::max<long long>(g.m, 1));
+    hipLaunchKernelGGL(k_hot_hist, dim3(blocks_for(n, kHotSpan)), dim3(kBlock), 0, c.s, g, N, hist.p);
+    GG_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_hot_threshold, dim3(S), dim3(kBlock), 0, c.s, hist.p, kPrHotK, thr.p);
+    GG_CHECK_LAUNCH();
+    for (int pass = 0; pass < 2; pass++) {
+        hipLaunchKernelGGL(k_hot_assign, dim3(blocks_for(n, kBlock, 16384)), dim3(kBlock), 0, c.s, g, N, kPrHotK,
+                           thr.p, pass, nslot.p, pb.hot_slot.p);
+        GG_CHECK_LAUNCH();
+    }
+    if (g.m > 0) {
+        hipLaunchKernelGGL(k_hot_encode, dim3(blocks_for(g.m, kBlock, 16384)), dim3(kBlock), 0, c.s, pb.col_ptr,
+                           (long long)g.m, N, kPrHotK, pb.hot_slot.p, pb.hcol.p);
+        GG_CHECK_LAUNCH();
+    }
+    GG_HIP(hipStreamSynchronize(c.s));  // the temporaries are freed on return
+    pb.hot_k = kPrHotK;
+}
+
 // Build (once per graph and segment width) the STRICT pull layout: S = 1 uses
 // the graph's own CSR; S > 1 the source-segmented CSRs.
 static PullBlocked &pull_layout(Ctx &c, Graph &G, int N) {
@@ -444,6 +610,7 @@ static PullBlocked &pull_layout(Ctx &c, Graph &G, int N) {
         total_chunks += nc;
     }
     pb->chunk_rows.ensure((size_t)std::max(2 * total_chunks, 2ll));
+    build_hot_cache(c, g, *pb);
     for (int s = 0; s < S; s++) {
         if (pb->nchunks[s] == 0) continue;
         hipLaunchKernelGGL(k_pr_partition, dim3(blocks_for(pb->nchunks[s], kBlock, 4096)), dim3(kBlock), 0, c.s,
@@ -481,6 +648,18 @@ double pull_layout_prepare(Graph &G, int32_t seg_vertices, hipStream_t stream) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return ms;
+}
+
+// resident workgroups of a STRICT kernel (each loads its LDS copy once)
+template <int HK>
+static long long strict_grid(int num_cus) {
+    static const int occ = [] {
+        int o = 0;
+        GG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, (const void *)k_pr_strict_chunks<HK>,
+                                                            kWave * kPrWaves, 0));
+        return o > 0 ? o : 1;
+    }();
+    return (long long)occ * num_cus;
 }
 
 void pr_run(Graph &G, const gg_schedule &sch, float damping, int iters, uint32_t flags, float *rank,
@@ -521,10 +700,15 @@ void pr_run(Graph &G, const gg_schedule &sch, float damping, int iters, uint32_t
         ws->pr_head.ensure((size_t)maxc);
         ws->pr_tail.ensure((size_t)maxc);
     }
+    const bool cached = strict && !(flags & GG_PR_NO_LDS_CACHE) && pb->hot_k == kPrHotK;
+    if (cached) {
+        ws->pr_hot[0].ensure((size_t)pb->S * kPrHotK);
+        ws->pr_hot[1].ensure((size_t)pb->S * kPrHotK);
+    }
     KernelTimer kt;
     kt.on = st && (st->flags & GG_STATS_TIME_KERNELS);
     kt.s = c.s;
-    const char *kname = push ? "k_pr_push_edges" : strict ? "k_pr_strict_chunks"
+    const char *kname = push ? "k_pr_push_edges" : cached ? "k_pr_strict_chunks (LDS cache)" : strict ? "k_pr_strict_chunks"
                         : lb == GG_LB_WM ? "k_pr_pull_wm" : lb == GG_LB_ETWC ? "k_pr_pull_etwc" : "k_pr_pull_vp";
     GG_HIP(hipEventRecord(e0, c.s));
 
@@ -534,8 +718,10 @@ void pr_run(Graph &G, const gg_schedule &sch, float damping, int iters, uint32_t
     a.dangling = (flags & GG_PR_NO_DANGLING) ? 0 : 1;
     a.partials = ws->pr_partial.p;
     a.acc = (strict || push) ? ws->pr_acc.p : nullptr;
+    a.hot_slot = cached ? pb->hot_slot.p : nullptr;
     // round 0
     a.contrib_out = ws->pr_contrib[0].p;
+    a.hot_out = cached ? ws->pr_hot[0].p : nullptr;
     a.rank_out = iters == 0 ? rank : nullptr;
     a.D_out = ws->pr_dangling.p + 0;
     hipLaunchKernelGGL(k_pr_init, dim3(nblk), dim3(kBlock), 0, c.s, a);
@@ -549,6 +735,8 @@ void pr_run(Graph &G, const gg_schedule &sch, float damping, int iters, uint32_t
         a.D_in = ws->pr_dangling.p + (t & 1);
         a.D_out = ws->pr_dangling.p + ((t + 1) & 1);
         a.rank_out = t == iters - 1 ? rank : nullptr;
+        const float *hot_in = cached ? ws->pr_hot[t & 1].p : nullptr;
+        a.hot_out = cached ? ws->pr_hot[(t + 1) & 1].p : nullptr;
         if (push) {
             if (eb) {
                 for (size_t sg = 0; sg + 1 < eb->seg_start.size(); sg++) {
@@ -575,12 +763,22 @@ void pr_run(Graph &G, const gg_schedule &sch, float damping, int iters, uint32_t
                 const long long nc = pb->nchunks[sg];
                 if (nc == 0) continue;
                 const int32_t *rp = pb->rp_ptr + (pb->S == 1 ? 0 : (size_t)sg * (n + 1));
-                const int32_t *cl = pb->col_ptr + pb->col_base[sg];
                 const int32_t *cr = pb->chunk_rows.p + 2 * pb->chunk_base[sg];
                 kt.begin();
-                hipLaunchKernelGGL(k_pr_strict_chunks, dim3((unsigned)std::min<long long>(nc, 65535)), dim3(kBlock), 0,
-                                   c.s, rp, cl, pb->m_s[sg], a.contrib_in, cr, ws->pr_acc.p, ws->pr_head.p,
-                                   ws->pr_tail.p, nc);
+                const long long groups = (nc + kPrWaves - 1) / kPrWaves;
+                if (cached) {
+                    hipLaunchKernelGGL((k_pr_strict_chunks<kPrHotK>),
+                                       dim3((unsigned)std::min<long long>(groups, strict_grid<kPrHotK>(c.num_cus))),
+                                       dim3(kWave * kPrWaves), 0, c.s, rp, pb->hcol.p + pb->col_base[sg],
+                                       pb->m_s[sg], a.contrib_in, hot_in + (size_t)sg * kPrHotK, cr, ws->pr_acc.p,
+                                       ws->pr_head.p, ws->pr_tail.p, nc);
+                } else {
+                    hipLaunchKernelGGL((k_pr_strict_chunks<0>),
+                                       dim3((unsigned)std::min<long long>(groups, strict_grid<0>(c.num_cus))),
+                                       dim3(kWave * kPrWaves), 0, c.s, rp, pb->col_ptr + pb->col_base[sg],
+                                       pb->m_s[sg], a.contrib_in, nullptr, cr, ws->pr_acc.p, ws->pr_head.p,
+                                       ws->pr_tail.p, nc);
+                }
                 kt.end();
                 GG_CHECK_LAUNCH();
                 hipLaunchKernelGGL(k_pr_fixup, dim3(blocks_for(nc, kBlock, 4096)), dim3(kBlock), 0, c.s, rp,
