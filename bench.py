@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, GB/s
 PR_SEGMENT = 1 << 20   # PageRank pull EdgeBlocking: source segments of 2^20 vertices
-PR_LDS_SOURCES = 8192  # highest-degree sources per segment the STRICT kernel keeps in LDS
+PR_LDS_SOURCES = 12288 # highest-degree sources per segment the STRICT kernel keeps in LDS
 
 
 def measured_traffic(kernel_src: str, summary: str, schedule_tag: str):

@@ -38,7 +38,7 @@ namespace gg {
 
 constexpr int kPrChunk = kWave * 8;   // STRICT: edges per chunk (one wavefront's)
 constexpr int kPrWaves = 16;          // STRICT: wavefronts per workgroup
-constexpr int kPrHotK = 8192;         // STRICT: highest-degree sources per segment cached in LDS
+constexpr int kPrHotK = 12288;        // STRICT: highest-degree sources per segment cached in LDS (48 KB)
 constexpr int kHotBins = 4096;        // degree histogram bins (the last one collects the rest)
 
 struct PrArgs {
