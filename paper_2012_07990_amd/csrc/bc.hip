@@ -193,25 +193,18 @@ __global__ __launch_bounds__(kBlock) void k_bc_pull(DevGraph g, int32_t *depth, 
 // order). The multi-source pass uses the same rule, so results are bitwise
 // identical between single and batched runs.
 
-__device__ __forceinline__ double bc_term(const DevGraph &g, int e, int dv1, double sv, const int32_t *depth,
-                                          const unsigned long long *sigma, const double *delta, double acc) {
-    const int w = g.col[e];
-    return depth[w] == dv1 ? bc_step(acc, sv, (double)sigma[w], delta[w]) : acc;
-}
-
-// The terms of edges e0, e0 + stride, ... below e_end, in that order, with the
-// loads of kEdgeBatch edges issued before their steps (the order of the
-// steps, and so the rounding, is the plain loop's). DT: the depth array read
-// for the successor test (one byte per vertex when the levels fit, so the
-// array stays in L2).
+// The sum of t(w) over the successors w among edges e0, e0 + stride, ...
+// below e_end, in that order, with the loads of kEdgeBatch edges issued
+// before their additions (the order of the additions, and so the rounding, is
+// the plain loop's). DT: the depth array read for the successor test (one
+// byte per vertex when the levels fit, so the array stays in L2).
 template <class DT>
-__device__ __forceinline__ double bc_terms(const DevGraph &g, int e0, int e_end, int stride, DT dv1, double sv,
-                                           const DT *depth, const unsigned long long *sigma,
-                                           const double *delta, double acc) {
+__device__ __forceinline__ double bc_terms(const DevGraph &g, int e0, int e_end, int stride, DT dv1,
+                                           const DT *depth, const double *tv, double acc) {
     for (int e = e0; e < e_end; e += kEdgeBatch * stride) {
         int ww[kEdgeBatch];
         DT dd[kEdgeBatch];
-        double sg[kEdgeBatch], dl[kEdgeBatch];
+        double tt[kEdgeBatch];
 #pragma unroll
         for (int b = 0; b < kEdgeBatch; b++) {
             const int eb = e + b * stride;
@@ -222,21 +215,26 @@ __device__ __forceinline__ double bc_terms(const DevGraph &g, int e0, int e_end,
 #pragma unroll
         for (int b = 0; b < kEdgeBatch; b++) {
             const bool on = e + b * stride < e_end && dd[b] == dv1;
-            sg[b] = on ? (double)sigma[ww[b]] : 1.0;
-            dl[b] = on ? delta[ww[b]] : 0.0;
+            tt[b] = on ? tv[ww[b]] : 0.0;
         }
 #pragma unroll
         for (int b = 0; b < kEdgeBatch; b++)
-            if (e + b * stride < e_end && dd[b] == dv1) acc = bc_step(acc, sv, sg[b], dl[b]);
+            if (e + b * stride < e_end && dd[b] == dv1) acc = acc + tt[b];
     }
     return acc;
+}
+
+__device__ __forceinline__ void bc_set(double *delta, double *tv, int v, double sv, double sum_t) {
+    const double d = bc_delta(sv, sum_t);
+    delta[v] = d;
+    tv[v] = bc_tval(sv, d);
 }
 
 // the vertices of level L (ids in level_ids); dv1 = L + 1 in the type of dep
 template <class DT>
 __global__ __launch_bounds__(kBlock) void k_bc_backward(DevGraph g, const int32_t *level_ids, int count,
                                                         const DT *dep, DT dv1, const unsigned long long *sigma,
-                                                        double *delta, int src) {
+                                                        double *delta, double *tv, int src) {
     __shared__ int q_v[2][kBlock];
     __shared__ int q_n[2];
     __shared__ double s_w[kBlock / kWave];
@@ -251,8 +249,7 @@ __global__ __launch_bounds__(kBlock) void k_bc_backward(DevGraph g, const int32_
             if (v == src) {
                 delta[v] = 0.0;
             } else if (deg < kBcWaveDeg) {
-                const double sv = (double)sigma[v];
-                delta[v] = bc_terms(g, g.row_ptr[v], g.row_ptr[v + 1], 1, dv1, sv, dep, sigma, delta, 0.0);
+                bc_set(delta, tv, v, (double)sigma[v], bc_terms(g, g.row_ptr[v], g.row_ptr[v + 1], 1, dv1, dep, tv, 0.0));
             } else {
                 const int k = atomicAdd(&q_n[deg < kBcBlockDeg ? 0 : 1], 1);
                 q_v[deg < kBcBlockDeg ? 0 : 1][k] = v;
@@ -261,15 +258,13 @@ __global__ __launch_bounds__(kBlock) void k_bc_backward(DevGraph g, const int32_
         __syncthreads();
         for (int k = wib; k < q_n[0]; k += kBlock / kWave) {
             const int v = q_v[0][k];
-            const double sv = (double)sigma[v];
-            double acc = bc_terms(g, g.row_ptr[v] + lane, g.row_ptr[v + 1], kWave, dv1, sv, dep, sigma, delta, 0.0);
+            double acc = bc_terms(g, g.row_ptr[v] + lane, g.row_ptr[v + 1], kWave, dv1, dep, tv, 0.0);
             acc = wave_sum(acc);
-            if (lane == 0) delta[v] = acc;
+            if (lane == 0) bc_set(delta, tv, v, (double)sigma[v], acc);
         }
         for (int k = 0; k < q_n[1]; k++) {
             const int v = q_v[1][k];
-            const double sv = (double)sigma[v];
-            double acc = bc_terms(g, g.row_ptr[v] + tid, g.row_ptr[v + 1], kBlock, dv1, sv, dep, sigma, delta, 0.0);
+            double acc = bc_terms(g, g.row_ptr[v] + tid, g.row_ptr[v + 1], kBlock, dv1, dep, tv, 0.0);
             acc = wave_sum(acc);
             __syncthreads();
             if (lane == 0) s_w[wib] = acc;
@@ -277,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_bc_backward(DevGraph g, const int32_
             if (tid == 0) {
                 double t = 0.0;
                 for (int w = 0; w < kBlock / kWave; w++) t += s_w[w];
-                delta[v] = t;
+                bc_set(delta, tv, v, (double)sigma[v], t);
             }
         }
         __syncthreads();
@@ -315,9 +310,10 @@ void bc_run(Graph &G, int32_t src, const gg_schedule &sch, uint64_t *sigma_out, 
     ws->bitmap[0].ensure(nb / 64);
     ws->aux_i32[3].ensure(n);  // depth
     ws->aux_f64[0].ensure(n);  // delta (fp64)
+    ws->aux_f64[1].ensure(n);  // t = (1 + delta) / sigma, written with delta
     ws->h_i32.ensure(16);
     int32_t *order = ws->q[0].p, *depth = ws->aux_i32[3].p, *ctr = ws->counters.p;
-    double *delta = ws->aux_f64[0].p;
+    double *delta = ws->aux_f64[0].p, *tv = ws->aux_f64[1].p;
     fill_i32(c, ctr, 64, 0);
     hipLaunchKernelGGL(k_bc_init, dim3(blocks_for(n, kBlock, 8192)), dim3(kBlock), 0, c.s, depth, sigma, delta, n,
                        src, order);
@@ -369,7 +365,7 @@ void bc_run(Graph &G, int32_t src, const gg_schedule &sch, uint64_t *sigma_out, 
     GG_HIP(hipStreamSynchronize(c.s));
     require(ws->h_i32.p[2] == 0, GG_ERR_OUT_OF_MEMORY, "BC frontier overflow");
     require(ws->h_i32.p[3] == 0, GG_ERR_OVERFLOW, "a shortest-path count exceeds 2^64-1");
-    // backward, deepest level first (the deepest level's delta stays 0)
+    // backward, deepest level first
     const int levels = (int)off.size() - 2;
     const bool small = levels < 255;  // depths 0..254 fit a byte next to the 255 marker
     uint8_t *d8 = ws->boolmap[0].p;   // free after the forward pass (nb >= n bytes)
@@ -378,14 +374,15 @@ void bc_run(Graph &G, int32_t src, const gg_schedule &sch, uint64_t *sigma_out, 
         GG_CHECK_LAUNCH();
         c.launches++;
     }
-    for (int L = levels - 2; L >= 0; L--) {
+    // from the deepest level (no successors: delta 0, t = 1/sigma) up
+    for (int L = levels - 1; L >= 0; L--) {
         const int cnt = off[L + 1] - off[L];
         if (small)
             hipLaunchKernelGGL(k_bc_backward<uint8_t>, dim3(blocks_for(cnt, kBlock, 16384)), dim3(kBlock), 0, c.s, g,
-                               order + off[L], cnt, (const uint8_t *)d8, (uint8_t)(L + 1), sigma, delta, src);
+                               order + off[L], cnt, (const uint8_t *)d8, (uint8_t)(L + 1), sigma, delta, tv, src);
         else
             hipLaunchKernelGGL(k_bc_backward<int32_t>, dim3(blocks_for(cnt, kBlock, 16384)), dim3(kBlock), 0, c.s, g,
-                               order + off[L], cnt, (const int32_t *)depth, (int32_t)(L + 1), sigma, delta, src);
+                               order + off[L], cnt, (const int32_t *)depth, (int32_t)(L + 1), sigma, delta, tv, src);
         GG_CHECK_LAUNCH();
         c.launches++;
     }

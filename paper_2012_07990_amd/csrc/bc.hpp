@@ -9,13 +9,19 @@ namespace gg {
 
 constexpr int kBcWaveDeg = 64, kBcBlockDeg = 4096;
 
-// acc + sigma(v)/sigma(w) * (1 + delta(w)) with no contraction into FMA, so
-// every kernel rounds this expression the same way
-__device__ __forceinline__ double bc_step(double acc, double sv, double sw, double dw) {
+// Brandes' dependency delta(v) = sum over successors w of sigma(v)/sigma(w) *
+// (1 + delta(w)) is evaluated as sigma(v) * sum_w t(w) with
+// t(w) = (1 + delta(w)) / sigma(w): each vertex stores t once its delta is
+// final, and a predecessor gathers one value per successor edge instead of
+// sigma(w) and delta(w). No contraction into FMA, so every kernel rounds the
+// same way.
+__device__ __forceinline__ double bc_tval(double sw, double dw) {
 #pragma clang fp contract(off)
-    const double q = sv / sw;
-    const double t = q * (1.0 + dw);
-    return acc + t;
+    return (1.0 + dw) / sw;
+}
+__device__ __forceinline__ double bc_delta(double sv, double sum_t) {
+#pragma clang fp contract(off)
+    return sv * sum_t;
 }
 
 }  // namespace gg

@@ -216,9 +216,15 @@ __device__ __forceinline__ void msbc_level(const DevGraph &g, int K, u64 all, u6
 }
 
 // ---- multi-source BC backward level (same summation order as the single pass) -----------
+__device__ __forceinline__ void ms_bc_set(double *delta_vm, double *t_vm, size_t i, double sv, double sum_t) {
+    const double d = bc_delta(sv, sum_t);
+    delta_vm[i] = d;
+    t_vm[i] = bc_tval(sv, d);
+}
+
 __device__ __forceinline__ void msbc_backward_level(const DevGraph &g, int K, const int32_t *srcs,
                                                     const int32_t *depth_vm, const u64 *sigma_vm, double *delta_vm,
-                                                    int level, Tid t) {
+                                                    double *t_vm, int level, Tid t) {
     __shared__ int q_v[2][kBlock];
     __shared__ int q_n[2];
     __shared__ double s_w[kBcGroup][kBlock / kWave];
@@ -248,12 +254,11 @@ __device__ __forceinline__ void msbc_backward_level(const DevGraph &g, int K, co
 #pragma unroll
                         for (int j = 0; j < kBcGroup; j++)
                             if (((mask >> j) & 1u) && depth_vm[(size_t)w * K + j] == level + 1)
-                                acc[j] = bc_step(acc[j], sv[j], (double)sigma_vm[(size_t)w * K + j],
-                                                 delta_vm[(size_t)w * K + j]);
+                                acc[j] = acc[j] + t_vm[(size_t)w * K + j];
                     }
 #pragma unroll
                     for (int j = 0; j < kBcGroup; j++)
-                        if ((mask >> j) & 1u) delta_vm[(size_t)v * K + j] = acc[j];
+                        if ((mask >> j) & 1u) ms_bc_set(delta_vm, t_vm, (size_t)v * K + j, sv[j], acc[j]);
                 } else {
                     const int t = deg < kBcBlockDeg ? 0 : 1;
                     q_v[t][atomicAdd(&q_n[t], 1)] = v;
@@ -278,13 +283,12 @@ __device__ __forceinline__ void msbc_backward_level(const DevGraph &g, int K, co
 #pragma unroll
                 for (int j = 0; j < kBcGroup; j++)
                     if (((mask >> j) & 1u) && depth_vm[(size_t)w * K + j] == level + 1)
-                        acc[j] = bc_step(acc[j], sv[j], (double)sigma_vm[(size_t)w * K + j],
-                                         delta_vm[(size_t)w * K + j]);
+                        acc[j] = acc[j] + t_vm[(size_t)w * K + j];
             }
 #pragma unroll
             for (int j = 0; j < kBcGroup; j++) {
                 const double r = wave_sum(acc[j]);
-                if (lane == 0 && ((mask >> j) & 1u)) delta_vm[(size_t)vv * K + j] = r;
+                if (lane == 0 && ((mask >> j) & 1u)) ms_bc_set(delta_vm, t_vm, (size_t)vv * K + j, sv[j], r);
             }
         }
         // the whole workgroup per vertex
@@ -304,8 +308,7 @@ __device__ __forceinline__ void msbc_backward_level(const DevGraph &g, int K, co
 #pragma unroll
                 for (int j = 0; j < kBcGroup; j++)
                     if (((mask >> j) & 1u) && depth_vm[(size_t)w * K + j] == level + 1)
-                        acc[j] = bc_step(acc[j], sv[j], (double)sigma_vm[(size_t)w * K + j],
-                                         delta_vm[(size_t)w * K + j]);
+                        acc[j] = acc[j] + t_vm[(size_t)w * K + j];
             }
             __syncthreads();
 #pragma unroll
@@ -317,7 +320,7 @@ __device__ __forceinline__ void msbc_backward_level(const DevGraph &g, int K, co
             if (tid < kBcGroup && ((mask >> tid) & 1u)) {
                 double t = 0.0;
                 for (int w = 0; w < kBlock / kWave; w++) t += s_w[tid][w];
-                delta_vm[(size_t)vv * K + tid] = t;
+                ms_bc_set(delta_vm, t_vm, (size_t)vv * K + tid, (double)sigma_vm[(size_t)vv * K + tid], t);
             }
         }
         __syncthreads();
@@ -336,8 +339,8 @@ __global__ __launch_bounds__(kBlock) void k_msbc_pull(DevGraph g, int K, u64 all
 }
 __global__ __launch_bounds__(kBlock) void k_msbc_backward(DevGraph g, int K, const int32_t *srcs,
                                                           const int32_t *depth_vm, const u64 *sigma_vm,
-                                                          double *delta_vm, int level) {
-    msbc_backward_level(g, K, srcs, depth_vm, sigma_vm, delta_vm, level, Tid::here());
+                                                          double *delta_vm, double *t_vm, int level) {
+    msbc_backward_level(g, K, srcs, depth_vm, sigma_vm, delta_vm, t_vm, level, Tid::here());
 }
 
 // ---- one persistent launch per batch (fused schedules): levels separated by grid barriers --
@@ -351,6 +354,7 @@ struct MsPullArgs {
     int32_t *depth_vm;
     u64 *sigma_vm;      // BC only
     double *delta_vm;   // BC only
+    double *t_vm;       // BC only: (1 + delta) / sigma
     const int32_t *srcs;
     int32_t *flags;
     GridBarrier bar;
@@ -377,8 +381,8 @@ __global__ __launch_bounds__(kBlock) void k_ms_pull_fused(MsPullArgs a) {
     }
     // levels 0 .. level-1 hold vertices
     if constexpr (BC) {
-        for (int L = level - 2; ok && L >= 0; L--) {
-            msbc_backward_level(a.g, a.K, a.srcs, a.depth_vm, a.sigma_vm, a.delta_vm, L, t);
+        for (int L = level - 1; ok && L >= 0; L--) {
+            msbc_backward_level(a.g, a.K, a.srcs, a.depth_vm, a.sigma_vm, a.delta_vm, a.t_vm, L, t);
             if (!grid_sync(bar)) ok = false;
         }
     }
@@ -402,12 +406,12 @@ static MsBuffers ms_buffers(Workspace &ws, int n, int K) {
 // launch; returns the number of levels run. Flags land in ws.h_i32[0..7].
 template <bool BC>
 static int ms_pull_persistent(Ctx &c, Graph &G, Workspace &ws, int K, u64 all, const MsBuffers &b, u64 *sig,
-                              double *del, const int32_t *srcs) {
+                              double *del, double *tv, const int32_t *srcs) {
     const void *kern = (const void *)k_ms_pull_fused<BC>;
     // every level sweeps all vertices: many waves per compute unit hide the
     // gathers' latency, at a barrier cost that grows with the workgroups
     const int blocks = fused_grid(kern, 4, c.num_cus);
-    MsPullArgs a{G.view(), K, all, b.visited, b.front, b.next, b.depth_vm, sig, del, srcs, ws.counters.p,
+    MsPullArgs a{G.view(), K, all, b.visited, b.front, b.next, b.depth_vm, sig, del, tv, srcs, ws.counters.p,
                  prepare_barrier(c, ws, blocks)};
     void *args[] = {&a};
     launch_cooperative(c, kern, blocks, args);
@@ -446,7 +450,7 @@ void msbfs_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &sch, int
     const u64 all = k == 64 ? ~0ull : ((1ull << k) - 1);
     if (sch.s1.kernel_fusion) {
         fill_i32(c, ws->counters.p, 8, 0);
-        const int levels = ms_pull_persistent<false>(c, G, *ws, k, all, b, nullptr, nullptr, nullptr);
+        const int levels = ms_pull_persistent<false>(c, G, *ws, k, all, b, nullptr, nullptr, nullptr, nullptr);
         if (st) { st->iterations = levels; st->pull_iterations = levels; st->fused = 1; }
     } else {
         for (int level = 1;; level++) {
@@ -491,6 +495,8 @@ void msbc_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &sch, uint
         sig.ensure((size_t)n * K);
         DevBuf<double> &del = ws->aux_f64[1];
         del.ensure((size_t)n * K);
+        DevBuf<double> &tv = ws->aux_f64[0];  // (1 + delta) / sigma, written with delta
+        tv.ensure((size_t)n * K);
         hipLaunchKernelGGL(k_ms_init, dim3(blocks_for(n, kBlock, 8192)), dim3(kBlock), 0, c.s, n, K, dsrc.p + j0,
                            b.visited, b.front, b.depth_vm, sig.p, del.p);
         GG_CHECK_LAUNCH();
@@ -498,7 +504,7 @@ void msbc_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &sch, uint
         const u64 all = (1ull << K) - 1;
         if (sch.s1.kernel_fusion) {
             fill_i32(c, ws->counters.p, 8, 0);
-            const int levels = ms_pull_persistent<true>(c, G, *ws, K, all, b, sig.p, del.p, dsrc.p + j0);
+            const int levels = ms_pull_persistent<true>(c, G, *ws, K, all, b, sig.p, del.p, tv.p, dsrc.p + j0);
             if (st) { st->iterations += levels; st->pull_iterations += levels; st->fused = 1; }
             require(ws->h_i32.p[3] == 0, GG_ERR_OVERFLOW, "a shortest-path count exceeds 2^64-1");
         } else {
@@ -517,9 +523,10 @@ void msbc_run(Graph &G, const int32_t *srcs, int k, const gg_schedule &sch, uint
                 if (ws->h_i32.p[0] == 0) break;
                 levels = level + 1;
             }
-            for (int level = levels - 2; level >= 0; level--) {
+            // from the deepest level (no successors: delta 0, t = 1/sigma) up
+            for (int level = levels - 1; level >= 0; level--) {
                 hipLaunchKernelGGL(k_msbc_backward, dim3(blocks_for(n, kBlock, 16384)), dim3(kBlock), 0, c.s, g, K,
-                                   dsrc.p + j0, b.depth_vm, sig.p, del.p, level);
+                                   dsrc.p + j0, b.depth_vm, sig.p, del.p, tv.p, level);
                 GG_CHECK_LAUNCH();
                 c.launches++;
             }
