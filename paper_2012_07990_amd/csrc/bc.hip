@@ -249,7 +249,8 @@ __global__ __launch_bounds__(kBlock) void k_bc_backward(DevGraph g, const int32_
             if (v == src) {
                 delta[v] = 0.0;
             } else if (deg < kBcWaveDeg) {
-                bc_set(delta, tv, v, (double)sigma[v], bc_terms(g, g.row_ptr[v], g.row_ptr[v + 1], 1, dv1, dep, tv, 0.0));
+                const double sum_t = bc_terms(g, g.row_ptr[v], g.row_ptr[v + 1], 1, dv1, dep, tv, 0.0);
+                bc_set(delta, tv, v, (double)sigma[v], sum_t);
             } else {
                 const int k = atomicAdd(&q_n[deg < kBcBlockDeg ? 0 : 1], 1);
                 q_v[deg < kBcBlockDeg ? 0 : 1][k] = v;

@@ -364,8 +364,18 @@ __global__ __launch_bounds__(kBlock) void k_pr_fixup(const int32_t *rp, long lon
         const long long rb = rp[r], re = rp[r + 1];
         if (re <= E1 || rb < E0) continue;  // fixed up by the chunk where the row starts
         const long long c1 = (re - 1) / kPrChunk;
+        // a hub's row covers many chunks: eight head loads are issued ahead of
+        // their additions, which keep the chunk order
         double sum = tail[c];
-        for (long long k = c + 1; k < c1; k++) sum += head[k];
+        long long k = c + 1;
+        for (; k + 8 <= c1; k += 8) {
+            double h[8];
+#pragma unroll
+            for (int b = 0; b < 8; b++) h[b] = head[k + b];
+#pragma unroll
+            for (int b = 0; b < 8; b++) sum += h[b];
+        }
+        for (; k < c1; k++) sum += head[k];
         sum += head[c1];
         accum[r] += sum;
     }
@@ -708,8 +718,11 @@ void pr_run(Graph &G, const gg_schedule &sch, float damping, int iters, uint32_t
     KernelTimer kt;
     kt.on = st && (st->flags & GG_STATS_TIME_KERNELS);
     kt.s = c.s;
-    const char *kname = push ? "k_pr_push_edges" : cached ? "k_pr_strict_chunks (LDS cache)" : strict ? "k_pr_strict_chunks"
-                        : lb == GG_LB_WM ? "k_pr_pull_wm" : lb == GG_LB_ETWC ? "k_pr_pull_etwc" : "k_pr_pull_vp";
+    const char *kname = push     ? "k_pr_push_edges"
+                        : cached ? "k_pr_strict_chunks (LDS cache)"
+                        : strict ? "k_pr_strict_chunks"
+                        : lb == GG_LB_WM ? "k_pr_pull_wm"
+                        : lb == GG_LB_ETWC ? "k_pr_pull_etwc" : "k_pr_pull_vp";
     GG_HIP(hipEventRecord(e0, c.s));
 
     PrArgs a{};
