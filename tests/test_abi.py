@@ -59,3 +59,23 @@ def test_null_graph_rejected():
 def test_preset_rejects_unknown():
     s = gg.Schedule()
     assert gg._lib.gg_schedule_preset(0, 99, ctypes.byref(s)) == gg.ERR_INVALID_ARG
+
+
+def test_python_constants_match_the_header():
+    """Every GG_* #define and enumerator in include/gg.h has the same value
+    under its unprefixed name in the Python binding."""
+    import os
+    import re
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "gg.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", " ", hdr, flags=re.S)
+    found = {}
+    for name, val in re.findall(r"#define\s+GG_(\w+)\s+(\d+)u?\b", hdr):
+        found[name] = int(val)
+    for body in re.findall(r"typedef\s+enum\s*\{(.*?)\}", hdr, flags=re.S):
+        for name, val in re.findall(r"GG_(\w+)\s*=\s*(\d+)", body):
+            found[name] = int(val)
+    assert "PR_NO_LDS_CACHE" in found and "LB_EDGE_ONLY" in found
+    missing = [n for n in found if not hasattr(gg, n)]
+    assert not missing, "binding lacks %s" % missing
+    wrong = {n: (found[n], getattr(gg, n)) for n in found if getattr(gg, n) != found[n]}
+    assert not wrong, wrong
