@@ -41,20 +41,6 @@ static gg_status guarded(Fn &&fn) {
 
 namespace gg {
 
-size_t Workspace::bytes() const {
-    size_t b = 0;
-    for (auto &x : q) b += x.n * sizeof(int32_t);
-    for (auto &x : boolmap) b += x.n;
-    for (auto &x : bitmap) b += x.n * 8;
-    b += tags.n * 4 + dedup_bits.n * 8 + dedup_bytes.n * 4 + bins.n * 4 + scan.n * 8 + scan_part.n * 8;
-    for (auto &x : aux_i32) b += x.n * 4;
-    for (auto &x : aux_u64) b += x.n * 8;
-    for (auto &x : aux_f32) b += x.n * 4;
-    for (auto &x : aux_f64) b += x.n * 8;
-    b += member.n + counters.n * 4;
-    return b;
-}
-
 std::unique_ptr<Workspace> Graph::acquire() {
     std::lock_guard<std::mutex> lk(mu);
     if (!pool.empty()) {

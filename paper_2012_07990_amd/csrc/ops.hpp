@@ -130,7 +130,6 @@ struct Workspace {
     DevBuf<unsigned> barrier;             // grid barrier state for fused kernels
     HostPinned<int32_t> h_i32;            // pinned readback slots
     HostPinned<long long> h_i64;
-    size_t bytes() const;
 };
 
 // ---- graph ------------------------------------------------------------------------------

@@ -16,7 +16,7 @@
 //                      that cross a chunk boundary are completed from the
 //                      chunks' head/tail partial sums in the vertex apply.
 //                      Each workgroup keeps a copy of the contributions of
-//                      the segment's kPrHotK highest-degree sources in LDS
+//                      the segment's kPrHotK (at most) highest-degree sources in LDS
 //                      (refreshed by the vertex apply every round): edges
 //                      from those sources read LDS instead of issuing a
 //                      random 4-byte global gather (the same values in the
@@ -259,11 +259,11 @@ __device__ __forceinline__ void wave_lds_sync() {
 // chunk's first and last rows also leave their in-chunk partial sums in
 // head[c] / tail[c], which k_pr_fixup adds for the rows that span chunks.
 // With HK > 0 the column entries of cached sources hold ~slot and their values
-// come from the HK-entry LDS copy of `hot`, loaded once per workgroup (the
-// grid is sized to stay resident).
+// come from an LDS copy of the segment's nhot (<= HK, a multiple of 4) entries
+// of `hot`, loaded once per workgroup (the grid is sized to stay resident).
 template <int HK>
 __global__ __launch_bounds__(kWave *kPrWaves) __attribute__((amdgpu_waves_per_eu(8))) void k_pr_strict_chunks(
-    const int32_t *rp, const int32_t *col, long long m, const float *contrib, const float *hot,
+    const int32_t *rp, const int32_t *col, long long m, const float *contrib, const float *hot, int nhot,
     const int32_t *chunk_rows, double *accum, double *head, double *tail, long long nchunks) {
     __shared__ float vals[kPrWaves][kPrChunk];
     __shared__ float4 hot_s4[HK > 0 ? HK / 4 : 1];
@@ -271,7 +271,7 @@ __global__ __launch_bounds__(kWave *kPrWaves) __attribute__((amdgpu_waves_per_eu
     const int lane = lane_id(), wib = (int)threadIdx.x / kWave;
     if constexpr (HK > 0) {
         const float4 *h4 = reinterpret_cast<const float4 *>(hot);
-        for (int i = threadIdx.x; i < HK / 4; i += kWave * kPrWaves) hot_s4[i] = h4[i];
+        for (int i = threadIdx.x; i < nhot / 4; i += kWave * kPrWaves) hot_s4[i] = h4[i];
         __syncthreads();
     }
     float *cv = vals[wib];
@@ -542,6 +542,9 @@ __global__ __launch_bounds__(kBlock) void k_hot_encode(const int32_t *col, long 
 
 static void build_hot_cache(Ctx &c, const DevGraph &g, PullBlocked &pb) {
     const int n = g.n, S = pb.S, N = pb.S == 1 ? std::max(n, 1) : pb.N;
+    // slots per segment: no more than the segment has vertices (rounded up to
+    // whole float4 loads), so narrow segments keep the tables O(n)
+    const int K = (int)std::min<long long>(kPrHotK, ((long long)N + 3) / 4 * 4);
     DevBuf<int32_t> hist, thr, nslot;
     hist.ensure((size_t)S * kHotBins);
     thr.ensure(S);
@@ -552,20 +555,20 @@ static void build_hot_cache(Ctx &c, const DevGraph &g, PullBlocked &pb) {
     pb.hcol.ensure((size_t)std::max<long long>(g.m, 1));
     hipLaunchKernelGGL(k_hot_hist, dim3(blocks_for(n, kHotSpan)), dim3(kBlock), 0, c.s, g, N, hist.p);
     GG_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_hot_threshold, dim3(S), dim3(kBlock), 0, c.s, hist.p, kPrHotK, thr.p);
+    hipLaunchKernelGGL(k_hot_threshold, dim3(S), dim3(kBlock), 0, c.s, hist.p, K, thr.p);
     GG_CHECK_LAUNCH();
     for (int pass = 0; pass < 2; pass++) {
-        hipLaunchKernelGGL(k_hot_assign, dim3(blocks_for(n, kBlock, 16384)), dim3(kBlock), 0, c.s, g, N, kPrHotK,
+        hipLaunchKernelGGL(k_hot_assign, dim3(blocks_for(n, kBlock, 16384)), dim3(kBlock), 0, c.s, g, N, K,
                            thr.p, pass, nslot.p, pb.hot_slot.p);
         GG_CHECK_LAUNCH();
     }
     if (g.m > 0) {
         hipLaunchKernelGGL(k_hot_encode, dim3(blocks_for(g.m, kBlock, 16384)), dim3(kBlock), 0, c.s, pb.col_ptr,
-                           (long long)g.m, N, kPrHotK, pb.hot_slot.p, pb.hcol.p);
+                           (long long)g.m, N, K, pb.hot_slot.p, pb.hcol.p);
         GG_CHECK_LAUNCH();
     }
     GG_HIP(hipStreamSynchronize(c.s));  // the temporaries are freed on return
-    pb.hot_k = kPrHotK;
+    pb.hot_k = K;
 }
 
 // Build (once per graph and segment width) the STRICT pull layout: S = 1 uses
@@ -710,10 +713,12 @@ void pr_run(Graph &G, const gg_schedule &sch, float damping, int iters, uint32_t
         ws->pr_head.ensure((size_t)maxc);
         ws->pr_tail.ensure((size_t)maxc);
     }
-    const bool cached = strict && !(flags & GG_PR_NO_LDS_CACHE) && pb->hot_k == kPrHotK;
+    const bool cached = strict && !(flags & GG_PR_NO_LDS_CACHE) && pb->hot_k > 0;
     if (cached) {
-        ws->pr_hot[0].ensure((size_t)pb->S * kPrHotK);
-        ws->pr_hot[1].ensure((size_t)pb->S * kPrHotK);
+        if (pb->hot_k > kPrHotK || pb->hot_k % 4 != 0)
+            throw Error(GG_ERR_DEVICE, "PageRank LDS cache: bad slot count per segment");
+        ws->pr_hot[0].ensure((size_t)pb->S * pb->hot_k);
+        ws->pr_hot[1].ensure((size_t)pb->S * pb->hot_k);
     }
     KernelTimer kt;
     kt.on = st && (st->flags & GG_STATS_TIME_KERNELS);
@@ -783,13 +788,13 @@ void pr_run(Graph &G, const gg_schedule &sch, float damping, int iters, uint32_t
                     hipLaunchKernelGGL((k_pr_strict_chunks<kPrHotK>),
                                        dim3((unsigned)std::min<long long>(groups, strict_grid<kPrHotK>(c.num_cus))),
                                        dim3(kWave * kPrWaves), 0, c.s, rp, pb->hcol.p + pb->col_base[sg],
-                                       pb->m_s[sg], a.contrib_in, hot_in + (size_t)sg * kPrHotK, cr, ws->pr_acc.p,
-                                       ws->pr_head.p, ws->pr_tail.p, nc);
+                                       pb->m_s[sg], a.contrib_in, hot_in + (size_t)sg * pb->hot_k, pb->hot_k, cr,
+                                       ws->pr_acc.p, ws->pr_head.p, ws->pr_tail.p, nc);
                 } else {
                     hipLaunchKernelGGL((k_pr_strict_chunks<0>),
                                        dim3((unsigned)std::min<long long>(groups, strict_grid<0>(c.num_cus))),
                                        dim3(kWave * kPrWaves), 0, c.s, rp, pb->col_ptr + pb->col_base[sg],
-                                       pb->m_s[sg], a.contrib_in, nullptr, cr, ws->pr_acc.p, ws->pr_head.p,
+                                       pb->m_s[sg], a.contrib_in, nullptr, 0, cr, ws->pr_acc.p, ws->pr_head.p,
                                        ws->pr_tail.p, nc);
                 }
                 kt.end();

@@ -1,5 +1,6 @@
 // Schedule defaults, presets and validation (SimpleGPUSchedule and
 // HybridGPUSchedule tables of the Scheduling Language section).
+#include <algorithm>
 #include <string>
 
 #include "algos.hpp"
@@ -144,12 +145,14 @@ size_t workspace_bytes(const Graph &g, int algo, int k) {
     switch (algo) {
     case GG_ALGO_SSSP: b += 2 * n * 4; break;
     case GG_ALGO_PR: b += 3 * n * 4; break;
-    case GG_ALGO_BC: b += n * 8 + n * 8; break;
+    case GG_ALGO_BC: b += 3 * n * 8; break;  // delta, t = (1 + delta) / sigma, one-byte depths
     default: break;
     }
     if (k > 1) {
         b += 3 * n * 8;  // multi-source masks
-        if (algo == GG_ALGO_BC) b += (size_t)k * n * 8 + n * 4;
+        if (algo == GG_ALGO_BFS) b += (size_t)k * n * 4;  // per-source depths, vertex-major
+        // per group of up to 16 sources: sigma, delta and t (8 B each) and depth (4 B)
+        if (algo == GG_ALGO_BC) b += (size_t)std::min(k, 16) * n * 28;
         if (algo == GG_ALGO_SSSP) b += (size_t)k * n * 4 + 2 * n * 4;
     }
     return b;
