@@ -271,6 +271,16 @@ gg_status gg_bc_multi(gg_graph *g, const int32_t *srcs_host, int32_t k, const gg
 gg_status gg_autotune(gg_graph *g, int32_t algo, double budget_s, const int32_t *probe_srcs, int32_t nprobe,
                       gg_stream_t stream, gg_schedule *out, double *best_ms);
 
+/* The tuned-schedule cache of g (the one gg_autotune fills and, with
+   budget_s <= 0, returns). gg_tuned_set seeds it with a schedule found
+   earlier, e.g. one stored under the graph's checksum by a previous process;
+   the schedule is validated for `algo` on g (GG_ERR_UNSUPPORTED_SCHEDULE
+   otherwise) and `ms` is kept as its measured time. gg_tuned_get copies the
+   cached schedule of `algo` to *out (and its time to *ms, may be NULL);
+   GG_ERR_NOT_FOUND when nothing is cached. Host-only: no device work. */
+gg_status gg_tuned_set(gg_graph *g, int32_t algo, const gg_schedule *s, double ms);
+gg_status gg_tuned_get(gg_graph *g, int32_t algo, gg_schedule *out, double *ms);
+
 /* Device bytes of workspace a query of `algo` with k sources needs on g. */
 gg_status gg_workspace_bytes(const gg_graph *g, int32_t algo, int32_t k, size_t *out);
 

@@ -126,6 +126,8 @@ _sig("gg_bfs_multi", [_P, _P, _i32, _SP, _P, _P, _STP])
 _sig("gg_sssp_multi", [_P, _P, _i32, _SP, _P, _P, _STP])
 _sig("gg_bc_multi", [_P, _P, _i32, _SP, _P, _P, _P, _STP])
 _sig("gg_workspace_bytes", [_P, _i32, _i32, ctypes.POINTER(ctypes.c_size_t)])
+_sig("gg_tuned_set", [_P, _i32, _SP, ctypes.c_double])
+_sig("gg_tuned_get", [_P, _i32, _SP, ctypes.POINTER(ctypes.c_double)])
 _sig("gg_autotune", [_P, _i32, ctypes.c_double, _P, _i32, _P, _SP, ctypes.POINTER(ctypes.c_double)])
 
 
@@ -438,6 +440,99 @@ class Graph:
         out = ctypes.c_size_t()
         _check(_lib.gg_workspace_bytes(self.handle, algo, k, ctypes.byref(out)), "gg_workspace_bytes")
         return out.value
+
+    # -- the tuned-schedule cache (gg_tuned_set / gg_tuned_get) -----------------------
+    def tuned(self, algo: int):
+        """(schedule, ms) cached for `algo` on this graph, or None."""
+        s, ms = Schedule(), ctypes.c_double()
+        st = _lib.gg_tuned_get(self.handle, int(algo), ctypes.byref(s), ctypes.byref(ms))
+        if st == ERR_NOT_FOUND:
+            return None
+        _check(st, "gg_tuned_get")
+        return s, ms.value
+
+    def set_tuned(self, algo: int, sched: Schedule, ms: float = 0.0) -> None:
+        _check(_lib.gg_tuned_set(self.handle, int(algo), ctypes.byref(sched), float(ms)), "gg_tuned_set")
+
+    def save_tuned(self, path: str, checksum: str) -> int:
+        """Store every cached tuned schedule of this graph in the JSON file at
+        `path` under `checksum` (see csr_checksum); returns how many."""
+        k = 0
+        for algo in ALGO_NAMES:
+            t = self.tuned(algo)
+            if t is not None:
+                save_tuned(path, checksum, algo, t[0], t[1])
+                k += 1
+        return k
+
+    def load_tuned(self, path: str, checksum: str) -> int:
+        """Seed this graph's cache from the schedules stored under `checksum`;
+        returns how many."""
+        got = load_tuned(path, checksum)
+        for algo, (sched, ms) in got.items():
+            self.set_tuned(algo, sched, ms)
+        return len(got)
+
+
+# ---- tuned schedules kept across processes: JSON keyed by a graph checksum --------
+ALGO_NAMES = {ALGO_BFS: "bfs", ALGO_SSSP: "sssp", ALGO_CC: "cc", ALGO_PR: "pr", ALGO_BC: "bc"}
+
+
+def csr_checksum(n, row_ptr, col, w=None) -> str:
+    """Digest of a host CSR graph (sizes, offsets, columns and weights): the
+    key under which its tuned schedules are stored."""
+    import hashlib
+    rp = np.ascontiguousarray(np.asarray(row_ptr, dtype=np.int32))
+    c = np.ascontiguousarray(np.asarray(col, dtype=np.int32))
+    h = hashlib.blake2b(digest_size=16)
+    h.update(np.array([int(n), c.size, 0 if w is None else 1], dtype=np.int64).tobytes())
+    h.update(rp.tobytes())
+    h.update(c.tobytes())
+    if w is not None:
+        h.update(np.ascontiguousarray(np.asarray(w, dtype=np.uint32)).tobytes())
+    return h.hexdigest()
+
+
+def schedule_to_dict(s: Schedule) -> dict:
+    simple = lambda x: {f: int(getattr(x, f)) for f, _ in SimpleSchedule._fields_}  # noqa: E731
+    return {"hybrid": int(s.hybrid), "threshold": float(s.threshold), "s1": simple(s.s1), "s2": simple(s.s2)}
+
+
+def schedule_from_dict(d: dict) -> Schedule:
+    s = Schedule()
+    s.hybrid = int(d["hybrid"])
+    s.threshold = float(d["threshold"])
+    for part in ("s1", "s2"):
+        for f, _ in SimpleSchedule._fields_:
+            setattr(getattr(s, part), f, int(d[part][f]))
+    return s
+
+
+def _read_store(path: str) -> dict:
+    import json
+    if not os.path.exists(path):
+        return {}
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def save_tuned(path: str, checksum: str, algo: int, sched: Schedule, ms: float) -> None:
+    """Record (or replace) the tuned schedule of `algo` for the graph with
+    `checksum` in the JSON file at `path`, keeping its other entries."""
+    import json
+    data = _read_store(path)
+    data.setdefault(checksum, {})[ALGO_NAMES[int(algo)]] = {"schedule": schedule_to_dict(sched), "ms": float(ms)}
+    tmp = path + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def load_tuned(path: str, checksum: str) -> dict:
+    """{algo: (Schedule, ms)} stored for the graph with `checksum` ({} if none)."""
+    ids = {v: k for k, v in ALGO_NAMES.items()}
+    entry = _read_store(path).get(checksum, {})
+    return {ids[name]: (schedule_from_dict(e["schedule"]), float(e["ms"])) for name, e in entry.items()}
 
 
 class Server:

@@ -349,6 +349,30 @@ gg_status gg_autotune(gg_graph *g, int32_t algo, double budget_s, const int32_t 
     });
 }
 
+gg_status gg_tuned_set(gg_graph *g, int32_t algo, const gg_schedule *s, double ms) {
+    return guarded([&] {
+        check_graph(g);
+        require(s != nullptr, GG_ERR_INVALID_ARG, "schedule is NULL");
+        require(algo >= GG_ALGO_BFS && algo <= GG_ALGO_BC, GG_ERR_INVALID_ARG, "unknown algorithm");
+        validate_schedule(g->g, algo, *s);
+        std::lock_guard<std::mutex> lk(g->g.mu);
+        g->g.tuned[algo] = {*s, ms};
+    });
+}
+
+gg_status gg_tuned_get(gg_graph *g, int32_t algo, gg_schedule *out, double *ms) {
+    return guarded([&] {
+        check_graph(g);
+        require(out != nullptr, GG_ERR_INVALID_ARG, "out is NULL");
+        require(algo >= GG_ALGO_BFS && algo <= GG_ALGO_BC, GG_ERR_INVALID_ARG, "unknown algorithm");
+        std::lock_guard<std::mutex> lk(g->g.mu);
+        auto it = g->g.tuned.find(algo);
+        require(it != g->g.tuned.end(), GG_ERR_NOT_FOUND, "no tuned schedule cached for this algorithm");
+        *out = it->second.first;
+        if (ms) *ms = it->second.second;
+    });
+}
+
 gg_status gg_workspace_bytes(const gg_graph *g, int32_t algo, int32_t k, size_t *out) {
     return guarded([&] {
         check_graph(g);

@@ -160,3 +160,26 @@ def test_autotune_returns_valid_schedule(algo):
     elif algo == gg.ALGO_BC:
         sig, _ = G.bc(src, s)
         assert_int_equal(sig.cpu().numpy().view(np.uint64), oracle_bc(name, src)[0])
+
+
+def test_tuned_schedule_survives_a_new_graph_object(tmp_path):
+    """The autotuner's winner, saved as JSON under the graph's checksum, seeds
+    a fresh graph of the same CSR: gg_autotune with no budget returns it
+    unchanged, and it runs to the oracle's result."""
+    h = host_graph("rmat12")
+    G = dev_graph("rmat12")
+    src = graphgen.max_degree_vertex(h)
+    s, ms = G.autotune(gg.ALGO_BFS, budget_s=1.0, probes=[src])
+    key = gg.csr_checksum(h.n, h.row_ptr, h.col, h.w)
+    path = str(tmp_path / "tuned.json")
+    assert G.save_tuned(path, key) >= 1
+    G2 = gg.Graph.from_graphgen(h)
+    assert G2.tuned(gg.ALGO_BFS) is None
+    assert G2.load_tuned(path, key) >= 1
+    s2, ms2 = G2.autotune(gg.ALGO_BFS, budget_s=0.0)
+    assert bytes(s2) == bytes(s) and ms2 == pytest.approx(ms)
+    assert_int_equal(G2.bfs(src, s2).cpu().numpy(), oracle_bfs("rmat12", src))
+    with pytest.raises(gg.GGError) as e:
+        G2.set_tuned(gg.ALGO_PR, gg.make_schedule(lb="vp", direction=gg.PUSH))
+    assert e.value.status == gg.ERR_UNSUPPORTED_SCHEDULE
+    G2.close()
