@@ -366,7 +366,7 @@ def main():
         "metric": "GTEPS per algorithm (BFS/SSSP/CC/PR/BC); batched queries/s + p99 latency",
         "value": round(value, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "int32 (BFS/SSSP/CC/BC sigma) + f32 (PR, BC delta)", "data": "synthetic",
+        "dtype": "int32 (BFS/SSSP/CC) + uint64 (BC sigma) + f64 sums of f32 values (PR, BC delta)", "data": "synthetic",
         "config": {"workload": "rmat%d ef16 a.57/b.19/c.19/d.05 symmetrised: BFS(DO)+SSSP(delta)+CC+PR(20)+BC"
                    % args.scale, "n": g.n, "m": g.m, "source": src, "algorithms": algos,
                    "parallelism": "single-gpu"},
