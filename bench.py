@@ -63,20 +63,21 @@ def parse():
     p.add_argument("--verbose", action="store_true")
     p.add_argument("--no-batched", action="store_true", help="skip the batched multi-source section")
     p.add_argument("--no-serving", action="store_true", help="skip the serving section")
-    p.add_argument("--serve-rates", default="500,5000", help="Poisson arrival rates (queries/s)")
-    p.add_argument("--serve-seconds", type=float, default=1.0)
+    p.add_argument("--serve-rates", default="100,500,1000,2000,5000", help="Poisson arrival rates (queries/s)")
+    p.add_argument("--serve-seconds", type=float, default=5.0, help="seconds of arrivals per rate")
+    p.add_argument("--serve-baseline-s", type=float, default=5.0,
+                   help="wall-clock cap of the one-query-per-launch baseline at each rate")
     p.add_argument("--serve-budget-s", type=float, default=150.0, help="wall-clock cap of the serving section")
-    p.add_argument("--grid", type=int, default=0,
-                   help="also time BFS/SSSP on a WxW road-like grid (fused vs unfused, delta sweep)")
-    p.add_argument("--grid-deltas", default="1,8,64,512",
-                   help="delta values of the grid SSSP runs (an unfused run is skipped when the fused one took > 20 s)")
+    p.add_argument("--grid", type=int, default=4096,
+                   help="side of the road-like grid for the BFS/SSSP fused-vs-unfused and delta runs (0: skip)")
+    p.add_argument("--grid-deltas", default="1,8,64,512", help="delta values of the grid SSSP runs")
+    p.add_argument("--grid-unfused-cap-s", type=float, default=4.0,
+                   help="skip the unfused run of a grid configuration whose fused run took longer than this")
     p.add_argument("--tune", action="store_true",
                    help="also run the autotuner per algorithm on R-MAT 22 and report its picks beside the step's schedules")
     p.add_argument("--tune-budget-s", type=float, default=8.0, help="autotuner wall-clock budget per algorithm")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy three times (scales rocprofv3 FETCH_SIZE/WRITE_SIZE)")
-    p.add_argument("--serve-full", action="store_true",
-                   help="serve the full four-graph mix (adds R-MAT 23) at 100..5000 q/s")
     return p.parse_args()
 
 
@@ -227,17 +228,16 @@ def main():
         G.close()
         return
 
-    # traversed-edge numerators from one verified run of each algorithm
-    reached = None
-    edges = {}
+    # one run of each algorithm: its outputs are kept on the host and compared
+    # with the oracle's (cpu_baseline leg), and they give the traversed-edge
+    # numerators
+    outs = {}
     for a in algos:
         out = run(a, scheds[a])
         torch.cuda.synchronize()
-        if a == "bfs":
-            reached = out.cpu().numpy() >= 0
-    if reached is None:
-        d = G.bfs(src, scheds["bfs"]).cpu().numpy()
-        reached = d >= 0
+        outs[a] = tuple(x.cpu().numpy() for x in out) if isinstance(out, tuple) else out.cpu().numpy()
+    depth = outs["bfs"] if "bfs" in outs else G.bfs(src, scheds["bfs"]).cpu().numpy()
+    reached = depth >= 0
     reached_edges = int(deg[reached].sum())
     for a in algos:
         edges[a] = {"bfs": reached_edges, "sssp": reached_edges, "bc": reached_edges, "cc": g.m,
@@ -289,7 +289,11 @@ def main():
         torch.cuda.synchronize()
         per[a]["edges_examined"] = int(sc.edges_examined)
         per[a]["vertices_processed"] = int(sc.vertices_processed)
-        log("algo %-5s %9.3f ms  %8.2f GTEPS  (%s)" % (a, ms, edges[a] / ms / 1e6, st.as_dict()))
+        b = algorithmic_bytes(a, g, depth, scheds[a], sc)
+        per[a]["algorithmic_bytes"] = int(b)
+        per[a]["hbm_frac"] = round(b / (ms * 1e-3) / (PEAK_HBM_GBS * 1e9), 4)
+        log("algo %-5s %9.3f ms  %8.2f GTEPS  frac %.3f (%s)" % (a, ms, edges[a] / ms / 1e6, per[a]["hbm_frac"],
+                                                                  st.as_dict()))
 
     # the timed steps
     for _ in range(args.warmup):
@@ -350,15 +354,16 @@ def main():
 
     tuned = tune_section(gg, G, scheds, run, src, edges, torch, args) if args.tune else None
 
-    cpu = None
+    cpu, parity = None, None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(g, src, reached_edges)
+        cpu, parity = cpu_baseline(g, src, reached_edges, outs, algos)
     G.close()
     del G
+    del outs
 
     small = small_section(gg, graphgen, torch)
-    grid = grid_section(gg, graphgen, torch, args.grid, [int(x) for x in args.grid_deltas.split(",")]) \
-        if args.grid else None
+    grid = grid_section(gg, graphgen, torch, args.grid, [int(x) for x in args.grid_deltas.split(",")],
+                        args.grid_unfused_cap_s) if args.grid else None
     batched = None if args.no_batched else batched_section(gg, graphgen, torch)
     serving = None if args.no_serving else serving_section(gg, graphgen, torch, args)
 
@@ -376,6 +381,7 @@ def main():
             "in_pr_rounds": round(pr_eb_ms / (per["pr"]["ms"] / 20), 2)},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "parity": parity,
         "small": small,
         "tuned": tuned,
         "grid": grid,
@@ -383,6 +389,9 @@ def main():
         "serving": serving,
     }
     print(json.dumps(rec), flush=True)
+    if parity is not None and not parity["all"]:
+        log("PARITY FAILURE: the step's GPU outputs differ from the oracle's: %s" % parity)
+        sys.exit(1)
 
 
 def describe(gg, s):
@@ -464,41 +473,61 @@ def tune_section(gg, G, scheds, run, src, edges, torch, args):
     return out
 
 
-def grid_section(gg, graphgen, torch, W, deltas):
-    """High-diameter road-like grid: SSSP over the given deltas and BFS, each
-    fused (one persistent launch) and unfused (one launch per round; skipped
-    when the fused run already took over 20 s)."""
+def grid_section(gg, graphgen, torch, W, deltas, unfused_cap_s):
+    """High-diameter road-like grid (the kernel-fusion experiment's setting):
+    BFS and delta-stepping SSSP over the given deltas from the corner vertex,
+    each as one persistent launch (fused) and as one launch per round
+    (unfused; skipped when the fused run already took longer than
+    unfused_cap_s, since the unfused loop is several times slower). Every
+    delta and both forms must give the same distances (and BFS depths)."""
+    import numpy as np
     g = graphgen.grid(W)
     G = gg.Graph.from_graphgen(g)
     out = {"workload": "grid %dx%d, 10%% non-tree edges dropped, weights 1..999, source 0" % (W, W),
-           "n": g.n, "m": g.m, "runs": []}
+           "n": g.n, "m": g.m, "unfused_cap_s": unfused_cap_s, "runs": []}
+    # first calls allocate the workspaces (outside every timing)
+    G.bfs(0, gg.make_schedule(lb="cm", fusion=True))
+    G.sssp(0, gg.make_schedule(lb="cm", delta=4096, fusion=True))
+    G.sssp(0, gg.make_schedule(lb="cm", delta=4096))
+    torch.cuda.synchronize()
+    first = {}
+    identical = True
     for algo in ["bfs", "sssp"]:
         for delta in (deltas if algo == "sssp" else [0]):
             fused_ms = 0.0
             for fused in (True, False):
-                if not fused and fused_ms > 20000:
+                if not fused and fused_ms > 1e3 * unfused_cap_s:
                     log("grid: %s delta %d unfused skipped (fused run took %.1f s)" % (algo, delta, fused_ms / 1e3))
                     continue
                 sch = gg.make_schedule(lb="cm", delta=max(delta, 1), fusion=fused)
-                run = (lambda: G.sssp(0, sch, stats=st)) if algo == "sssp" else (lambda: G.bfs(0, sch, stats=st))
-                st = gg.Stats()
-                t1 = time.perf_counter()
-                run()
-                torch.cuda.synchronize()
-                ms = 1e3 * (time.perf_counter() - t1)
-                if ms < 20000:  # a second timed run when the first was not too long
+
+                def run(st):
+                    return G.sssp(0, sch, stats=st) if algo == "sssp" else G.bfs(0, sch, stats=st)
+                ts = []
+                for rep in range(3):
                     st = gg.Stats()
                     t1 = time.perf_counter()
-                    run()
+                    d = run(st)
                     torch.cuda.synchronize()
-                    ms = 1e3 * (time.perf_counter() - t1)
+                    ts.append(time.perf_counter() - t1)
+                    if ts[-1] > 2.0:  # long runs are timed once
+                        break
+                ms = 1e3 * sorted(ts)[len(ts) // 2]
+                d = d.cpu().numpy()
+                if algo not in first:
+                    first[algo] = d
+                same = bool(np.array_equal(d, first[algo]))
+                identical &= same
                 rec = {"algo": algo, "delta": delta if algo == "sssp" else None, "fused": fused, "ms": round(ms, 3),
                        "rounds": st.iterations, "buckets": st.buckets, "launches": st.launches,
-                       "us_per_round": round(1e3 * ms / max(st.iterations, 1), 2)}
+                       "us_per_round": round(1e3 * ms / max(st.iterations, 1), 2),
+                       "us_per_bucket": round(1e3 * ms / st.buckets, 2) if st.buckets else None,
+                       "timed_runs": len(ts), "same_as_first": same}
                 log("grid: %s" % rec)
                 out["runs"].append(rec)
                 if fused:
                     fused_ms = ms
+    out["identical_across_deltas_and_forms"] = identical
     G.close()
     return out
 
@@ -510,7 +539,7 @@ def batched_section(gg, graphgen, torch):
     g = graphgen.rmat(20, weights=True)
     G = gg.Graph.from_graphgen(g)
     deg = g.degrees()
-    bfs_src = graphgen.sample_sources(g, 64, 7)
+    bfs_src = graphgen.sample_giant_sources(g, 64, 7)
     bc_src = bfs_src[:16]
     sb = gg.schedule_preset(gg.ALGO_BFS, gg.PRESET_POWERLAW)
     sb.threshold = 0.01
@@ -552,7 +581,7 @@ def batched_section(gg, graphgen, torch):
     t_best = min(t_multi, t_levels)
     log("batched: persistent %.2f ms, launch per level %.2f ms, single %.2f ms, speedup %.2fx, identical=%s" %
         (t_multi * 1e3, t_levels * 1e3, t_single * 1e3, t_single / t_best, ok))
-    out = {"workload": "rmat20: 64 BFS + 16 BC sources (uniform over non-isolated vertices, seed 7)",
+    out = {"workload": "rmat20: 64 BFS + 16 BC sources (uniform over the largest component, seed 7)",
            "ms_batched": round(t_best * 1e3, 3), "ms_batched_persistent": round(t_multi * 1e3, 3),
            "ms_batched_launch_per_level": round(t_levels * 1e3, 3), "ms_single_calls": round(t_single * 1e3, 3),
            "speedup": round(t_single / t_best, 2), "gteps_batched": round(edges / t_best / 1e9, 2),
@@ -567,7 +596,7 @@ def batched_section(gg, graphgen, torch):
         if Gx is None:
             gh = graphgen.grid(2048)
             Gx = gg.Graph.from_graphgen(gh)
-            srcs = graphgen.sample_sources(gh, 64, 7)
+            srcs = graphgen.sample_giant_sources(gh, 64, 7)
         ms_s = gg.make_schedule(delta=ms_delta)
         st = gg.Stats()
         dm = Gx.sssp_multi(srcs, ms_s, stats=st)
@@ -604,23 +633,40 @@ def batched_section(gg, graphgen, torch):
 
 
 def serving_section(gg, graphgen, torch, args):
-    """Poisson streams of mixed BFS/SSSP/BC queries over resident graphs, served
-    with continuous batching, against one query per launch in arrival order."""
+    """Poisson streams of mixed BFS/SSSP/BC queries over four resident graphs
+    (R-MAT 18, 20 and 23 with weights, and the 2048^2 road-like grid), served
+    with continuous batching, against one query per launch in arrival order
+    on the same GPU under the same per-(graph, algorithm) schedules."""
     import numpy as np
-    gspecs = [("rmat18", lambda: graphgen.rmat(18, weights=True)), ("rmat20", lambda: graphgen.rmat(20, weights=True)),
-              ("grid2048", lambda: graphgen.grid(2048))]
-    if args.serve_full:
-        gspecs.append(("rmat23", lambda: graphgen.rmat(23, weights=True)))
-    hg = [f() for _, f in gspecs]
-    Gs = [gg.Graph.from_graphgen(g) for g in hg]
-    cand = [np.nonzero(g.degrees() > 0)[0] for g in hg]
-    rates = [float(x) for x in args.serve_rates.split(",")] if not args.serve_full else [100, 500, 1000, 2000, 5000]
+    specs = [("rmat18", lambda: graphgen.rmat(18, weights=True)),
+             ("rmat20", lambda: graphgen.rmat(20, weights=True)),
+             ("rmat23", lambda: graphgen.rmat(23, weights=True)),
+             ("grid2048", lambda: graphgen.grid(2048))]
+    Gs, cand, names = [], [], []
+    for name, f in specs:
+        t0 = time.perf_counter()
+        g = f()
+        Gs.append(gg.Graph.from_graphgen(g))
+        cand.append(graphgen.giant_component(g))
+        names.append(name)
+        log("serving: %s n=%d m=%d ready in %.1fs" % (name, g.n, g.m, time.perf_counter() - t0))
+        del g
+    is_rmat = [nm.startswith("rmat") for nm in names]
+    step = schedules(gg)
+    sched = []
+    for gi in range(len(Gs)):
+        if is_rmat[gi]:
+            sched.append({gg.ALGO_BFS: step["bfs"], gg.ALGO_SSSP: step["sssp"], gg.ALGO_BC: step["bc"]})
+        else:  # high diameter: persistent loops, wide buckets
+            sched.append({gg.ALGO_BFS: gg.make_schedule(lb="cm", fusion=True),
+                          gg.ALGO_SSSP: gg.make_schedule(lb="cm", delta=4096, fusion=True)})
+    rates = [float(x) for x in args.serve_rates.split(",")]
     rng = np.random.default_rng(11)
-    is_rmat = [name.startswith("rmat") for name, _ in gspecs]
+    algo_name = {gg.ALGO_BFS: "bfs", gg.ALGO_SSSP: "sssp", gg.ALGO_BC: "bc"}
 
     def make_stream(rate, seconds):
-        n = max(1, int(rate * seconds))
-        arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n))
+        k = max(1, int(rate * seconds))
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, size=k))
         qs = []
         for t in arrivals:
             gi = int(rng.integers(0, len(Gs)))
@@ -633,81 +679,85 @@ def serving_section(gg, graphgen, torch, args):
         return qs
 
     def pct(xs, p):
-        return float(np.percentile(np.asarray(xs), p)) if xs else None
+        return round(float(np.percentile(np.asarray(xs), p)), 3) if len(xs) else None
 
-    out = {"graphs": [name for name, _ in gspecs], "mix": "BFS 50% / SSSP 35% / BC 15% (BC on R-MAT only)",
-           "rates": []}
-    budget = 16 << 30
-    # per-graph schedules: power-law preset on R-MAT; on the high-diameter grid
-    # delta-stepping runs as one persistent loop (alone on the device) with wide
-    # buckets (delta 4096: fewer rounds, each paying a grid barrier)
-    grid_sssp = gg.make_schedule(lb="cm", delta=4096, fusion=True)
-    sec0 = time.perf_counter()
-    for rate in rates:
-        if time.perf_counter() - sec0 > args.serve_budget_s:
-            log("serving: wall-clock cap reached, rate %g skipped" % rate)
-            break
-        qs = make_stream(rate, args.serve_seconds)
+    def serve(qs, budget):
         srv = gg.Server(budget_bytes=budget, nstreams=4)
         gids = [srv.add_graph(G) for G in Gs]
-        for gi, (name, _) in enumerate(gspecs):
-            if name.startswith("grid"):
-                srv.set_schedule(gids[gi], gg.ALGO_SSSP, grid_sssp)
-        log("serving: rate %g, %d queries" % (rate, len(qs)))
+        for gi in range(len(Gs)):
+            for a, sc in sched[gi].items():
+                srv.set_schedule(gids[gi], a, sc)
         t0 = time.perf_counter()
         tickets = []
         for (ta, gi, algo, src) in qs:
             now = time.perf_counter() - t0
             if ta > now:
                 time.sleep(ta - now)
-            tickets.append(srv.submit(gids[gi], algo, src))
-        lat = []
+            tickets.append((srv.submit(gids[gi], algo, src), algo))
+        lat = {a: [] for a in algo_name}
         done = 0
-        for i, t in enumerate(tickets):
+        for i, (t, algo) in enumerate(tickets):
             r = srv.wait(t, 60.0)
             if r is None:
                 log("serving: query %d still running after 60 s, stopping the wait" % i)
                 break
-            lat.append(r["latency_ms"])
+            lat[algo].append(r["latency_ms"])
             done += 1
-            if done % 500 == 0:
-                log("serving: %d/%d done" % (done, len(tickets)))
         t_end = time.perf_counter() - t0
         st = srv.stats()
         srv.close()
-        served_qps = done / t_end
-        # baseline: one query per launch, in arrival order, on one stream
-        # (same schedules; bounded to 30 s of wall time)
-        sched = {gg.ALGO_BFS: gg.schedule_preset(gg.ALGO_BFS, gg.PRESET_POWERLAW),
-                 gg.ALGO_BC: gg.schedule_preset(gg.ALGO_BC, gg.PRESET_POWERLAW),
-                 gg.ALGO_SSSP: gg.schedule_preset(gg.ALGO_SSSP, gg.PRESET_POWERLAW)}
-        sched[gg.ALGO_SSSP].s1.delta = 64
-        blat = []
-        nb = 0
+        return done, t_end, lat, st
+
+    def baseline(qs, cap_s):
         t1 = time.perf_counter()
+        lat = []
         for (ta, gi, algo, src) in qs:
             now = time.perf_counter() - t1
-            if now > 30.0:
+            if now > cap_s:
                 break
             if ta > now:
                 time.sleep(ta - now)
-            G = Gs[gi]
+            G, sc = Gs[gi], sched[gi][algo]
             if algo == gg.ALGO_BFS:
-                G.bfs(src, sched[algo])
+                G.bfs(src, sc)
             elif algo == gg.ALGO_SSSP:
-                G.sssp(src, grid_sssp if gspecs[gi][0].startswith("grid") else sched[algo])
+                G.sssp(src, sc)
             else:
-                G.bc(src, sched[algo])
+                G.bc(src, sc)
             torch.cuda.synchronize()
-            blat.append((time.perf_counter() - t1 - ta) * 1e3)
-            nb += 1
-        tb = time.perf_counter() - t1
+            lat.append((time.perf_counter() - t1 - ta) * 1e3)
+        return len(lat), time.perf_counter() - t1, lat
+
+    budget = 16 << 30
+    out = {"graphs": names, "mix": "BFS 50% / SSSP 35% / BC 15% (BC on R-MAT only); graph uniform; source uniform "
+                                   "over the graph's largest component",
+           "budget_bytes": budget, "streams": 4, "seconds_per_rate": args.serve_seconds,
+           "schedules": {nm: {algo_name[a]: describe(gg, sc) for a, sc in sched[gi].items()}
+                         for gi, nm in enumerate(names)}, "rates": []}
+    # warm-up: every (graph, algorithm) once through the server and once alone
+    warm = [(0.0, gi, a, int(cand[gi][0])) for gi in range(len(Gs)) for a in sched[gi]]
+    serve(warm, budget)
+    baseline(warm, 1e9)
+    sec0 = time.perf_counter()
+    for rate in rates:
+        if time.perf_counter() - sec0 > args.serve_budget_s:
+            log("serving: wall-clock cap reached, rate %g skipped" % rate)
+            break
+        qs = make_stream(rate, args.serve_seconds)
+        log("serving: rate %g, %d queries" % (rate, len(qs)))
+        done, t_end, lat, st = serve(qs, budget)
+        served_qps = done / t_end
+        nb, tb, blat = baseline(qs, args.serve_baseline_s)
         base_qps = nb / tb
+        alll = sum(lat.values(), [])
         rec = {"rate_qps": rate, "queries": len(qs), "completed": done, "served_qps": round(served_qps, 1),
-               "p50_ms": round(pct(lat, 50), 3), "p99_ms": round(pct(lat, 99), 3),
-               "max_batch": st["max_batch"], "batches": st["batches"],
-               "baseline_qps": round(base_qps, 1), "baseline_p50_ms": round(pct(blat, 50), 3),
-               "baseline_p99_ms": round(pct(blat, 99), 3), "baseline_queries": nb,
+               "sustained": served_qps >= 0.95 * min(rate, len(qs) / max(qs[-1][0], 1e-9)),
+               "p50_ms": pct(alll, 50), "p99_ms": pct(alll, 99),
+               "per_algo": {algo_name[a]: {"queries": len(v), "p50_ms": pct(v, 50), "p99_ms": pct(v, 99)}
+                            for a, v in lat.items() if v},
+               "max_batch": st["max_batch"], "batches": st["batches"], "bytes_peak": st["bytes_peak"],
+               "baseline_qps": round(base_qps, 1), "baseline_p50_ms": pct(blat, 50),
+               "baseline_p99_ms": pct(blat, 99), "baseline_queries": nb,
                "throughput_ratio": round(served_qps / base_qps, 2)}
         log("serving rate %g: %s" % (rate, rec))
         out["rates"].append(rec)
@@ -716,21 +766,112 @@ def serving_section(gg, graphgen, torch, args):
     return out
 
 
-def cpu_baseline(g, src, reached_edges):
-    """The oracle (single-threaded C) on a bounded sample of the same workload."""
+def host_cpu():
+    """(CPU model, logical CPUs this process may run on)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count()
+    return model, avail
+
+
+def algorithmic_bytes(algo, g, depth, sched, st):
+    """Bytes the method itself must move for one run (the per-vertex and
+    per-edge figures of the byte model in the design doc), from the run's device
+    counters (examined edges, processed vertices) and the BFS level structure.
+    Hybrid runs: a level whose input frontier holds more than threshold * n
+    vertices is a PULL level (the HybridGPUSchedule rule); its edges are the
+    examined edges the PUSH levels do not account for."""
+    import numpy as np
+    n, m = g.n, g.m
+    deg = g.degrees()
+    E, V = float(st.edges_examined), float(st.vertices_processed)
+    if algo == "sssp":
+        return 20.0 * V + 12.0 * E
+    if algo == "cc":
+        return 12.0 * V + 8.0 * E
+    if algo == "pr":
+        return 20.0 * (16.0 * n + 8.0 * m)
+    # BFS and BC forward: replay the direction choice level by level
+    reached = depth >= 0
+    levels = int(depth.max()) + 1
+    F = np.bincount(depth[reached], minlength=levels).astype(np.float64)
+    Fe = np.bincount(depth[reached], weights=deg[reached].astype(np.float64), minlength=levels)
+    visited = np.cumsum(F)
+    push_b, pull_b, e_push = 0.0, 0.0, 0.0
+    for L in range(levels):
+        pull = bool(sched.hybrid) and F[L] > float(sched.threshold) * n
+        if pull:
+            pull_b += 12.0 * (n - visited[L]) + n / 8.0
+        else:
+            push_b += 20.0 * F[L]
+            e_push += Fe[L]
+    e_pull = max(E - e_push, 0.0)
+    fwd = push_b + 8.0 * e_push + pull_b + 4.125 * e_pull
+    if algo == "bfs":
+        return fwd
+    # BC: sigma per vertex and per examined edge forward; backward over every
+    # reached vertex's edges (column, depth, sigma, delta) and its delta
+    e_back = float(deg[reached].sum())
+    return fwd + 8.0 * float(reached.sum()) + 8.0 * E + 20.0 * e_back + 4.0 * float(reached.sum())
+
+
+def cpu_baseline(g, src, reached_edges, outs, algos):
+    """The oracle (single-threaded C, one core) on the step's whole workload:
+    the same graph and source, PageRank for all 20 rounds. Its outputs are the
+    reference the step's GPU outputs are compared with (depths, distances,
+    labels and path counts bit for bit; PageRank within max-abs 1e-6 and the
+    sum, L1 and relative checks; BC dependencies within relative 1e-4)."""
+    import numpy as np
     import oracle
-    t = {}
-    t0 = time.perf_counter(); oracle.bfs(g.n, g.row_ptr, g.col, src); t["bfs"] = time.perf_counter() - t0
-    t0 = time.perf_counter(); oracle.cc(g.n, g.row_ptr, g.col); t["cc"] = time.perf_counter() - t0
-    t0 = time.perf_counter(); oracle.pagerank(g.n, g.row_ptr, g.col, 0.85, 2); t["pr2"] = time.perf_counter() - t0
-    t0 = time.perf_counter(); oracle.sssp(g.n, g.row_ptr, g.col, g.w, src); t["sssp"] = time.perf_counter() - t0
-    t0 = time.perf_counter(); oracle.bc(g.n, g.row_ptr, g.col, src); t["bc"] = time.perf_counter() - t0
-    step_s = t["bfs"] + t["cc"] + 10 * t["pr2"] + t["sssp"] + t["bc"]
-    step_edges = 3 * reached_edges + g.m + 20 * g.m
-    return {"value": round(step_edges / step_s / 1e9, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
-            "sample": "one full step on the same graph and source, PageRank timed for 2 rounds and scaled to 20 "
-                      "(bfs %.2fs, cc %.2fs, pr2 %.2fs, sssp %.2fs, bc %.2fs)" %
-                      (t["bfs"], t["cc"], t["pr2"], t["sssp"], t["bc"])}
+    model, avail = host_cpu()
+    csr_code = oracle.check_csr(g.n, g.row_ptr, g.col)  # re-validation, not timed
+    calls = {"bfs": lambda: oracle.bfs(g.n, g.row_ptr, g.col, src),
+             "sssp": lambda: oracle.sssp(g.n, g.row_ptr, g.col, g.w, src),
+             "cc": lambda: oracle.cc(g.n, g.row_ptr, g.col),
+             "pr": lambda: oracle.pagerank(g.n, g.row_ptr, g.col, 0.85, 20),
+             "bc": lambda: oracle.bc(g.n, g.row_ptr, g.col, src)}
+    t, ref = {}, {}
+    for a in algos:
+        t0 = time.perf_counter()
+        ref[a] = calls[a]()
+        t[a] = time.perf_counter() - t0
+    step_s = sum(t.values())
+    step_edges = sum({"bfs": reached_edges, "sssp": reached_edges, "bc": reached_edges, "cc": g.m,
+                      "pr": 20 * g.m}[a] for a in algos)
+    par = {"csr_check": csr_code == 0}
+    for a in algos:
+        got, exp = outs[a], ref[a]
+        if a in ("bfs", "sssp", "cc"):
+            par[a] = bool(np.array_equal(got, exp))
+        elif a == "pr":
+            err = np.abs(got.astype(np.float64) - exp)
+            par[a] = bool(err.max() <= 1e-6 and err.sum() <= 1e-4 and (err / exp).max() <= 1e-3
+                          and abs(float(got.astype(np.float64).sum()) - 1.0) <= 1e-4)
+            par["pr_max_abs"] = float(err.max())
+        else:
+            sig, dl = got
+            es, ed = exp
+            ok_s = bool(np.array_equal(sig.view(np.uint64), es))
+            rel = np.abs(dl.astype(np.float64) - ed)
+            ok_d = bool((rel <= 1e-4 * np.abs(ed) + 1e-6).all())
+            par[a] = ok_s and ok_d
+    par["all"] = all(v for k, v in par.items() if isinstance(v, bool))
+    log("parity against the oracle: %s" % par)
+    cpu = {"value": round(step_edges / step_s / 1e9, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+           "nproc": avail, "cpu_model": model,
+           "sample": "one full step (%s) on the same graph and source, PageRank for all 20 rounds, one core (%s)" %
+                     ("+".join(algos), ", ".join("%s %.2fs" % (a, t[a]) for a in algos))}
+    return cpu, par
 
 
 if __name__ == "__main__":

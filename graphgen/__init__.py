@@ -225,3 +225,30 @@ def sample_sources(g: Graph, k: int, seed: int) -> np.ndarray:
             seen.add(j)
             out.append(int(cand[j]))
     return np.array(out, dtype=np.int32)
+
+
+def giant_component(g: Graph) -> np.ndarray:
+    """Vertex ids of the largest connected component, ascending (ties: the
+    component holding the smaller id). Input selection only, by scipy's
+    connected_components."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+    A = sp.csr_matrix((np.ones(g.m, dtype=np.int8), g.col, g.row_ptr), shape=(g.n, g.n))
+    _, lab = connected_components(A, directed=False)
+    sizes = np.bincount(lab)
+    return np.nonzero(lab == int(np.argmax(sizes)))[0].astype(np.int32)
+
+
+def sample_giant_sources(g: Graph, k: int, seed: int) -> np.ndarray:
+    """k distinct sources uniform over the largest connected component."""
+    cand = giant_component(g)
+    k = min(k, cand.size)
+    out, seen, ctr = [], set(), 0
+    while len(out) < k:
+        j = int((rng(seed, ctr) * cand.size) >> 64)
+        ctr += 1
+        if j not in seen:
+            seen.add(j)
+            out.append(int(cand[j]))
+    return np.array(out, dtype=np.int32)
+

@@ -33,6 +33,25 @@ import torch  # noqa: E402,F401
 
 _lib = ctypes.CDLL(LIB_PATH)
 
+# Library objects still open when the interpreter exits are closed by an
+# atexit hook, which runs before torch's own exit handlers (torch was imported
+# first, so its handlers were registered first and run last) and before
+# module teardown: device memory, streams and worker threads are released
+# while the HIP runtime is still up, servers before the graphs they serve.
+import atexit  # noqa: E402
+import weakref  # noqa: E402
+
+_live_servers = weakref.WeakSet()
+_live_graphs = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for s in list(_live_servers):
+        s.close()
+    for g in list(_live_graphs):
+        g.close()
+
 # ---- enums (mirror include/gg.h) --------------------------------------------------
 OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_UNSUPPORTED_SCHEDULE, ERR_OVERFLOW, \
     ERR_ADMISSION, ERR_NOT_FOUND, ERR_NOT_READY = range(9)
@@ -291,6 +310,7 @@ class Graph:
     def __init__(self, handle: ctypes.c_void_p, n: int, m: int, weighted: bool, symmetric: bool):
         self.handle = handle
         self.n, self.m, self.weighted, self.symmetric = n, m, weighted, symmetric
+        _live_graphs.add(self)
 
     @classmethod
     def from_csr(cls, n, row_ptr, col, w=None, symmetric=True, validate=False, stream=None) -> "Graph":
@@ -544,6 +564,7 @@ class Server:
         _check(_lib.gg_server_create(int(budget_bytes), int(nstreams), ctypes.byref(h)), "gg_server_create")
         self.handle = h
         self.graphs = []
+        _live_servers.add(self)
 
     def add_graph(self, G: Graph) -> int:
         gid = ctypes.c_int32()

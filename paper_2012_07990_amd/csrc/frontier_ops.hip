@@ -296,6 +296,9 @@ __global__ __launch_bounds__(kBlock) void k_build_coo(const int32_t *row_ptr, in
     }
 }
 
+// Built under the graph's lock and completed (stream synchronised) before the
+// lock is released: a query on another stream that finds the array already
+// present reads a finished array.
 void ensure_coo(Ctx &c, Graph &G) {
     std::lock_guard<std::mutex> lk(G.mu);
     if (G.coo_src.p) return;
@@ -303,7 +306,12 @@ void ensure_coo(Ctx &c, Graph &G) {
     if (G.m > 0) {
         hipLaunchKernelGGL(k_build_coo, dim3(blocks_for(G.n, kBlock / kWave, 16384)), dim3(kBlock), 0, c.s,
                            G.row_ptr.p, G.n, G.coo_src.p);
-        GG_CHECK_LAUNCH();
+        const hipError_t e = hipGetLastError();
+        const hipError_t e2 = e == hipSuccess ? hipStreamSynchronize(c.s) : e;
+        if (e2 != hipSuccess) {
+            G.coo_src.release();
+            GG_HIP(e2);
+        }
         c.launches++;
     }
 }

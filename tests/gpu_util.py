@@ -18,7 +18,17 @@ needs_gpu = pytest.mark.skipif(not HAS_GPU, reason="needs a GPU")
 
 @functools.lru_cache(maxsize=None)
 def host_graph(name: str):
-    """Named seeded test inputs (symmetric CSR, some weighted)."""
+    """Named seeded test inputs (symmetric CSR, some weighted), each
+    re-validated by the oracle's CSR check before any result is compared."""
+    g = _build_graph(name)
+    code = oracle.check_csr(g.n, g.row_ptr, g.col)
+    assert code == 0, "input %s fails the oracle's CSR check (code %d)" % (name, code)
+    if g.w is not None:
+        assert g.w.size == g.m and (g.w.size == 0 or int(g.w.min()) >= 1)
+    return g
+
+
+def _build_graph(name: str):
     if name.startswith("rmat"):
         return graphgen.rmat(int(name[4:]), weights=True)
     if name.startswith("grid"):

@@ -77,3 +77,17 @@ def test_sources():
     ks = graphgen.sample_sources(g, 64, 7)
     assert len(set(ks.tolist())) == 64 and (deg[ks] > 0).all()
     assert np.array_equal(ks, graphgen.sample_sources(g, 64, 7))
+
+
+def test_giant_component_sources():
+    g = graphgen.disjoint_cliques([3, 40, 5])
+    comp = graphgen.giant_component(g)
+    assert list(comp) == list(range(3, 43))
+    ks = graphgen.sample_giant_sources(g, 10, 7)
+    assert len(set(ks.tolist())) == 10 and ((ks >= 3) & (ks < 43)).all()
+    assert np.array_equal(ks, graphgen.sample_giant_sources(g, 10, 7))
+    h = graphgen.rmat(12)
+    lab = oracle.cc(h.n, h.row_ptr, h.col)
+    vals, counts = np.unique(lab, return_counts=True)
+    big = vals[np.argmax(counts)]
+    assert np.array_equal(graphgen.giant_component(h), np.nonzero(lab == big)[0])
