@@ -239,6 +239,7 @@ def main():
     depth = outs["bfs"] if "bfs" in outs else G.bfs(src, scheds["bfs"]).cpu().numpy()
     reached = depth >= 0
     reached_edges = int(deg[reached].sum())
+    edges = {}
     for a in algos:
         edges[a] = {"bfs": reached_edges, "sssp": reached_edges, "bc": reached_edges, "cc": g.m,
                     "pr": 20 * g.m}[a]

@@ -312,8 +312,11 @@ typedef struct {
 typedef struct {
     int64_t submitted, completed, collected, rejected, batches;
     int32_t max_batch;
-    size_t bytes_in_use, bytes_peak;
+    size_t bytes_in_use; /* running batches' workspaces + uncollected results */
+    size_t bytes_peak;   /* peak of bytes_in_use + bytes_idle at batch admission */
     double busy_ms;      /* summed wall time of executed batches */
+    size_t bytes_idle;   /* held between batches: pooled workspaces, derived layouts */
+    int64_t trims;       /* admissions that freed pooled workspaces first */
 } gg_serve_stats;
 
 #define GG_OUT_DEVICE 0u  /* `out` is device memory */

@@ -162,7 +162,8 @@ class Result(ctypes.Structure):
 class ServeStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("collected", ctypes.c_int64),
                 ("rejected", ctypes.c_int64), ("batches", ctypes.c_int64), ("max_batch", ctypes.c_int32),
-                ("bytes_in_use", ctypes.c_size_t), ("bytes_peak", ctypes.c_size_t), ("busy_ms", ctypes.c_double)]
+                ("bytes_in_use", ctypes.c_size_t), ("bytes_peak", ctypes.c_size_t), ("busy_ms", ctypes.c_double),
+                ("bytes_idle", ctypes.c_size_t), ("trims", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

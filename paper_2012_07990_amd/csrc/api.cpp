@@ -42,19 +42,66 @@ static gg_status guarded(Fn &&fn) {
 namespace gg {
 
 std::unique_ptr<Workspace> Graph::acquire() {
+    std::unique_ptr<Workspace> w;
     std::lock_guard<std::mutex> lk(mu);
     if (!pool.empty()) {
-        auto w = std::move(pool.back());
+        w = std::move(pool.back());
         pool.pop_back();
-        return w;
+    } else {
+        w = std::make_unique<Workspace>();
     }
-    return std::make_unique<Workspace>();
+    w->lease_bytes = w->bytes();
+    leased += w->lease_bytes;
+    return w;
 }
 
 void Graph::give_back(std::unique_ptr<Workspace> ws) {
     if (!ws) return;
+    std::unique_ptr<Workspace> drop;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        leased -= ws->lease_bytes;
+        ws->lease_bytes = 0;
+        if (pool.size() < 8) pool.push_back(std::move(ws));
+        else drop = std::move(ws);
+    }
+}
+
+size_t Graph::pooled_bytes() {
     std::lock_guard<std::mutex> lk(mu);
-    if (pool.size() < 8) pool.push_back(std::move(ws));
+    size_t b = leased;
+    for (auto &w : pool) b += w->bytes();
+    return b;
+}
+
+size_t Graph::layout_bytes() {
+    std::lock_guard<std::mutex> lk(mu);
+    size_t b = coo_src.bytes();
+    for (auto &kv : eb) b += kv.second->src.bytes() + kv.second->dst.bytes();
+    for (auto &kv : pull_eb) {
+        const PullBlocked &p = *kv.second;
+        b += p.rp.bytes() + p.col.bytes() + p.chunk_rows.bytes() + p.hot_slot.bytes() + p.hcol.bytes();
+    }
+    return b;
+}
+
+size_t Graph::trim_pool(size_t keep) {
+    std::vector<std::unique_ptr<Workspace>> drop;
+    size_t freed = 0;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        size_t held = leased;
+        for (auto &w : pool) held += w->bytes();
+        while (!pool.empty() && held > keep) {
+            const size_t b = pool.back()->bytes();
+            held -= b;
+            freed += b;
+            drop.push_back(std::move(pool.back()));
+            pool.pop_back();
+        }
+    }
+    drop.clear();  // the buffers are freed outside the lock
+    return freed;
 }
 
 }  // namespace gg

@@ -76,6 +76,8 @@ struct DevBuf {
         p = nullptr;
         n = 0;
     }
+    // device bytes held
+    size_t bytes() const { return p ? (n ? n : 1) * sizeof(T) : 0; }
     // grow-only allocation (contents not preserved)
     void ensure(size_t count) {
         if (count <= n && p) return;
@@ -130,6 +132,20 @@ struct Workspace {
     DevBuf<unsigned> barrier;             // grid barrier state for fused kernels
     HostPinned<int32_t> h_i32;            // pinned readback slots
     HostPinned<long long> h_i64;
+    size_t lease_bytes = 0;               // bytes() when it was last leased from the pool
+
+    // device bytes held by every buffer above
+    size_t bytes() const {
+        size_t b = counters.bytes() + tags.bytes() + dedup_bits.bytes() + dedup_bytes.bytes() + bins.bytes() +
+                   scan.bytes() + scan_part.bytes() + member.bytes() + pr_acc.bytes() + pr_head.bytes() +
+                   pr_tail.bytes() + pr_partial.bytes() + pr_dangling.bytes() + ms_sigma.bytes() + barrier.bytes();
+        for (int i = 0; i < 2; i++)
+            b += q[i].bytes() + boolmap[i].bytes() + bitmap[i].bytes() + aux_f64[i].bytes() + pr_contrib[i].bytes() +
+                 pr_hot[i].bytes();
+        for (int i = 0; i < 3; i++) b += aux_u64[i].bytes() + aux_f32[i].bytes();
+        for (int i = 0; i < 4; i++) b += aux_i32[i].bytes();
+        return b;
+    }
 };
 
 // ---- graph ------------------------------------------------------------------------------
@@ -168,6 +184,7 @@ struct Graph {
     std::map<int, std::pair<gg_schedule, double>> tuned;       // autotuner winners (schedule, ms) per algorithm
     std::mutex mu;
     std::vector<std::unique_ptr<Workspace>> pool;
+    size_t leased = 0;  // lease_bytes of the workspaces leased out now
     int device = 0;
     int num_cus = 256;
 
@@ -176,6 +193,14 @@ struct Graph {
     }
     std::unique_ptr<Workspace> acquire();
     void give_back(std::unique_ptr<Workspace> ws);
+    // device bytes held by the pooled workspaces plus those leased out (at
+    // their size when leased), and by the derived layouts built so far (COO
+    // sources, EdgeBlocked COO, pull blocking)
+    size_t pooled_bytes();
+    size_t layout_bytes();
+    // free pooled workspaces until at most `keep` bytes stay pooled;
+    // returns the bytes freed
+    size_t trim_pool(size_t keep);
 };
 
 // RAII lease of a workspace from the graph's pool

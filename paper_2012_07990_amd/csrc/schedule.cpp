@@ -140,12 +140,17 @@ void validate_schedule(const Graph &g, int algo, const gg_schedule &s) {
 }
 
 size_t workspace_bytes(const Graph &g, int algo, int k) {
-    const size_t n = (size_t)g.n, nb = (n + 255) / 256 * 256;
-    size_t b = 2 * n * 4 + 2 * nb + 2 * nb / 8 + n * 4 + 256;  // queues, maps, tags
+    // an upper bound of what one call may add to a workspace: pooled
+    // workspaces are shared by every schedule and algorithm, so the frontier
+    // part is the union over schedules (queues 8n, boolmaps 2n, bitmaps n/4,
+    // tags 4n, dedup maps 1.125n, STRICT degree scan 8n, TWC tiers 12n,
+    // EDGE_ONLY membership n, small counters)
+    const size_t n = (size_t)g.n + 256, m = (size_t)g.m;
+    size_t b = 37 * n + 65536;
     switch (algo) {
-    case GG_ALGO_SSSP: b += 2 * n * 4; break;
-    case GG_ALGO_PR: b += 3 * n * 4; break;
-    case GG_ALGO_BC: b += 3 * n * 8; break;  // delta, t = (1 + delta) / sigma, one-byte depths
+    case GG_ALGO_SSSP: b += 3 * n * 4; break;                   // far queues, far tags
+    case GG_ALGO_PR: b += 24 * n + m / 16 + 65536; break;        // contributions, fp64 sums, LDS-cache tables, chunk heads/tails
+    case GG_ALGO_BC: b += 4 * n + 2 * n * 8 + n; break;          // depth, delta and t, one-byte depths
     default: break;
     }
     if (k > 1) {

@@ -11,6 +11,7 @@
 // assumes no other kernel occupies the compute units.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <shared_mutex>
 
@@ -30,15 +31,21 @@ struct GpuExecutor : serve::Executor {
     // a persistent (fused) loop assumes the whole device: it runs alone
     std::shared_mutex device;
 
+    hipStream_t release_stream = nullptr;
+
     explicit GpuExecutor(int workers) {
         for (int i = 0; i < workers; i++) {
             hipStream_t s;
             GG_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
             streams.push_back(s);
         }
+        GG_HIP(hipStreamCreateWithFlags(&release_stream, hipStreamNonBlocking));
     }
     ~GpuExecutor() override {
+        for (auto s : streams) (void)hipStreamSynchronize(s);
+        if (release_stream) (void)hipStreamSynchronize(release_stream);
         for (auto s : streams) (void)hipStreamDestroy(s);
+        if (release_stream) (void)hipStreamDestroy(release_stream);
     }
 
     int max_batch(int algo) const override {
@@ -77,6 +84,26 @@ struct GpuExecutor : serve::Executor {
         return s;
     }
 
+    // Stream-ordered device buffer freed on every exit path.
+    struct AsyncBuf {
+        void *p = nullptr;
+        hipStream_t s;
+        explicit AsyncBuf(hipStream_t st) : s(st) {}
+        AsyncBuf(const AsyncBuf &) = delete;
+        ~AsyncBuf() {
+            if (p) (void)hipFreeAsync(p, s);
+        }
+    };
+
+    void fail(serve::Batch &b, hipStream_t st, int code) {
+        (void)hipStreamSynchronize(st);
+        for (auto *r : b.reqs) {
+            r->status = code;
+            if (r->result) (void)hipFreeAsync(r->result, st);
+            r->result = nullptr;
+        }
+    }
+
     void run(int worker, serve::Batch &b) override {
         hipStream_t st = streams[worker];
         Graph &G = *graphs[b.gid];
@@ -106,55 +133,74 @@ struct GpuExecutor : serve::Executor {
                     bc_run(G, r->src, s, (uint64_t *)r->result, (float *)((char *)r->result + 8 * n), st, nullptr);
                     break;
                 }
-            } else {
-                std::vector<int32_t> srcs;
-                for (auto *r : b.reqs) srcs.push_back(r->src);
-                void *stage = nullptr;
-                GG_HIP(hipMallocAsync(&stage, (size_t)k * result_bytes(b.gid, b.algo), st));
-                unsigned long long overflow = 0;
-                if (b.algo == GG_ALGO_BFS || b.algo == GG_ALGO_SSSP) {
-                    if (b.algo == GG_ALGO_BFS) msbfs_run(G, srcs.data(), k, s, (int32_t *)stage, st, nullptr);
-                    else mssssp_run(G, srcs.data(), k, s, (int32_t *)stage, st, nullptr, &overflow);
-                    for (int i = 0; i < k; i++)
-                        GG_HIP(hipMemcpyAsync(b.reqs[i]->result, (int32_t *)stage + i * n, 4 * n,
-                                              hipMemcpyDeviceToDevice, st));
-                } else {
-                    uint64_t *sig = (uint64_t *)stage;
-                    float *del = (float *)((char *)stage + 8 * n * k);
-                    msbc_run(G, srcs.data(), k, s, sig, del, st, nullptr);
-                    for (int i = 0; i < k; i++) {
-                        GG_HIP(hipMemcpyAsync(b.reqs[i]->result, sig + i * n, 8 * n, hipMemcpyDeviceToDevice, st));
-                        GG_HIP(hipMemcpyAsync((char *)b.reqs[i]->result + 8 * n, del + i * n, 4 * n,
-                                              hipMemcpyDeviceToDevice, st));
-                    }
-                }
-                GG_HIP(hipFreeAsync(stage, st));
                 GG_HIP(hipStreamSynchronize(st));
-                for (int i = 0; i < k; i++) {
-                    serve::Req *r = b.reqs[i];
-                    r->status = ((overflow >> i) & 1ull) ? GG_ERR_OVERFLOW : GG_OK;
-                    if (r->status != GG_OK) {
-                        (void)hipFree(r->result);
-                        r->result = nullptr;
-                    }
-                }
+                for (auto *r2 : b.reqs) r2->status = GG_OK;
                 return;
             }
-            GG_HIP(hipStreamSynchronize(st));
-            for (auto *r : b.reqs) r->status = GG_OK;
-        } catch (const Error &e) {
-            (void)hipStreamSynchronize(st);
-            for (auto *r : b.reqs) {
-                r->status = e.code;
-                if (r->result) (void)hipFree(r->result);
-                r->result = nullptr;
+            std::vector<int32_t> srcs;
+            for (auto *r : b.reqs) srcs.push_back(r->src);
+            AsyncBuf stage(st);
+            GG_HIP(hipMallocAsync(&stage.p, (size_t)k * result_bytes(b.gid, b.algo), st));
+            unsigned long long overflow = 0;
+            if (b.algo == GG_ALGO_BFS || b.algo == GG_ALGO_SSSP) {
+                if (b.algo == GG_ALGO_BFS) msbfs_run(G, srcs.data(), k, s, (int32_t *)stage.p, st, nullptr);
+                else mssssp_run(G, srcs.data(), k, s, (int32_t *)stage.p, st, nullptr, &overflow);
+                for (int i = 0; i < k; i++)
+                    GG_HIP(hipMemcpyAsync(b.reqs[i]->result, (int32_t *)stage.p + i * n, 4 * n,
+                                          hipMemcpyDeviceToDevice, st));
+            } else {
+                uint64_t *sig = (uint64_t *)stage.p;
+                float *del = (float *)((char *)stage.p + 8 * n * k);
+                msbc_run(G, srcs.data(), k, s, sig, del, st, nullptr);
+                for (int i = 0; i < k; i++) {
+                    GG_HIP(hipMemcpyAsync(b.reqs[i]->result, sig + i * n, 8 * n, hipMemcpyDeviceToDevice, st));
+                    GG_HIP(hipMemcpyAsync((char *)b.reqs[i]->result + 8 * n, del + i * n, 4 * n,
+                                          hipMemcpyDeviceToDevice, st));
+                }
             }
+            GG_HIP(hipStreamSynchronize(st));
+            for (int i = 0; i < k; i++) {
+                serve::Req *r = b.reqs[i];
+                r->status = ((overflow >> i) & 1ull) ? GG_ERR_OVERFLOW : GG_OK;
+                if (r->status != GG_OK) {
+                    (void)hipFreeAsync(r->result, st);
+                    r->result = nullptr;
+                }
+            }
+        } catch (const Error &e) {
+            fail(b, st, e.code);
+        } catch (const std::bad_alloc &) {
+            fail(b, st, GG_ERR_OUT_OF_MEMORY);
+        } catch (const std::exception &) {
+            fail(b, st, GG_ERR_DEVICE);
         }
     }
 
+    // results were complete on their worker's stream before the client saw
+    // them; they go back to the stream-ordered pool through the release stream
     void release(serve::Req &r) override {
-        if (r.result) (void)hipFree(r.result);
+        if (r.result) (void)hipFreeAsync(r.result, release_stream);
         r.result = nullptr;
+    }
+
+    size_t idle_bytes() override {
+        size_t b = 0;
+        for (int i = 0; i < ngraphs; i++) b += graphs[i]->pooled_bytes() + graphs[i]->layout_bytes();
+        return b;
+    }
+
+    // derived layouts stay; pooled workspaces are freed, largest graphs' first
+    void trim(size_t target) override {
+        size_t idle = idle_bytes();
+        std::vector<int> order;
+        for (int i = 0; i < ngraphs; i++) order.push_back(i);
+        std::sort(order.begin(), order.end(), [&](int a, int b2) { return graphs[a]->n > graphs[b2]->n; });
+        for (int i : order) {
+            if (idle <= target) break;
+            const size_t pooled = graphs[i]->pooled_bytes();
+            const size_t excess = idle - target;
+            idle -= graphs[i]->trim_pool(pooled > excess ? pooled - excess : 0);
+        }
     }
 };
 
@@ -294,6 +340,8 @@ gg_status gg_server_stats(gg_server *srv, gg_serve_stats *out) {
         out->bytes_in_use = s.bytes_in_use;
         out->bytes_peak = s.bytes_peak;
         out->busy_ms = s.busy_ms;
+        out->bytes_idle = s.bytes_idle;
+        out->trims = s.trims;
     });
 }
 

@@ -70,16 +70,23 @@ bool Core::form_batch(Batch &b) {
     std::vector<Req *> pick{head};
     for (auto it = pending_.begin() + 1; it != pending_.end() && (int)pick.size() < lim; ++it)
         if ((*it)->gid == head->gid && (*it)->algo == head->algo) pick.push_back(*it);
-    // shrink until the batch (work + results) fits
+    // shrink until the batch (work + results) fits beside the idle bytes,
+    // trimming idle memory that is in the way
+    size_t idle = ex_->idle_bytes();
     while (!pick.empty()) {
         const size_t need = ex_->work_bytes(head->gid, head->algo, (int)pick.size()) + pick.size() * head->result_bytes;
-        if (need <= free_bytes) {
+        if (need <= free_bytes && idle > free_bytes - need) {
+            ex_->trim(free_bytes - need);
+            idle = ex_->idle_bytes();
+            st_.trims++;
+        }
+        if (need <= free_bytes && idle <= free_bytes - need) {
             b.gid = head->gid;
             b.algo = head->algo;
             b.reqs = pick;
             b.work_bytes = ex_->work_bytes(head->gid, head->algo, (int)pick.size());
             in_use_ += need;
-            st_.bytes_peak = std::max(st_.bytes_peak, in_use_);
+            st_.bytes_peak = std::max(st_.bytes_peak, in_use_ + idle);
             for (Req *r : pick) pending_.erase(std::find(pending_.begin(), pending_.end(), r));
             return true;
         }
@@ -179,6 +186,7 @@ Stats Core::stats() {
     std::lock_guard<std::mutex> lk(mu_);
     Stats s = st_;
     s.bytes_in_use = in_use_;
+    s.bytes_idle = ex_->idle_bytes();
     return s;
 }
 

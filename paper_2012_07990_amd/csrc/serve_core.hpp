@@ -6,11 +6,14 @@
 // at submission. Worker threads (one per device stream) repeatedly take the
 // oldest pending query and add every other pending query for the same graph
 // and algorithm, up to the executor's batch limit and the memory still free
-// (budget minus running batches minus results not yet collected). A batch
-// that does not fit waits until memory frees up; queries that arrive while
-// others run are picked up by the next free worker, so batches of different
-// sizes run concurrently on different streams. A result stays charged to the
-// budget until the client collects it.
+// (budget minus running batches, results not yet collected and the bytes the
+// executor holds between batches). Idle bytes in the way of a batch are
+// trimmed first; a batch that still does not fit waits until memory frees
+// up. Queries that arrive while others run are picked up by the next free
+// worker, so batches of different sizes run concurrently on different
+// streams. A result stays charged to the budget until the client collects
+// it. Invariant: device bytes held <= in_use + idle <= budget, given that
+// work_bytes() bounds what a batch allocates beyond idle memory it reuses.
 #pragma once
 
 #include <chrono>
@@ -65,12 +68,20 @@ public:
     virtual void run(int worker, Batch &b) = 0;
     // free one collected result
     virtual void release(Req &r) = 0;
+    // device bytes held between batches (pooled workspaces, derived layouts
+    // of the served graphs): charged to the budget beside running batches
+    // and uncollected results
+    virtual size_t idle_bytes() { return 0; }
+    // free idle bytes (best effort) until idle_bytes() <= target
+    virtual void trim(size_t target) { (void)target; }
 };
 
 struct Stats {
     int64_t submitted = 0, completed = 0, rejected = 0, batches = 0, collected = 0;
     int32_t max_batch_seen = 0;
-    size_t bytes_in_use = 0, bytes_peak = 0;
+    size_t bytes_in_use = 0, bytes_peak = 0;  // running batches + uncollected results
+    size_t bytes_idle = 0;                    // held by the executor between batches
+    int64_t trims = 0;                        // batches that had idle memory freed first
     double busy_ms = 0;
 };
 

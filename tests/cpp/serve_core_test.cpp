@@ -1,7 +1,9 @@
 // CPU test of the serving core's policy with a fake executor (no device):
 // admission refusal, continuous batching per (graph, algorithm), the memory
 // budget (including uncollected results) and result delivery.
+#include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -146,6 +148,68 @@ static void test_concurrent_workers_overlap() {
     std::puts("ok overlap");
 }
 
+// An executor that keeps one workspace per finished batch (like a pool):
+// the core charges those idle bytes, trims them when a batch needs the room,
+// and held bytes (running + results + idle) never pass the budget.
+struct Pooling : Fake {
+    std::mutex mu;
+    size_t pooled = 0, held_peak = 0, running_bytes = 0;
+    std::atomic<int> trims{0};
+    size_t idle_bytes() override {
+        std::lock_guard<std::mutex> lk(mu);
+        return pooled;
+    }
+    void trim(size_t target) override {
+        std::lock_guard<std::mutex> lk(mu);
+        while (pooled > target && pooled >= work_per) pooled -= work_per;
+        if (pooled > target) pooled = 0;
+        trims++;
+    }
+    size_t outstanding = 0;  // results not yet released
+    void run(int w, Batch &b) override {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            // reuse a pooled workspace when there is one
+            const size_t reuse = pooled >= work_per ? work_per : 0;
+            pooled -= reuse;
+            running_bytes += work_per * b.reqs.size();
+            outstanding += result_per * b.reqs.size();
+            held_peak = std::max(held_peak, running_bytes + pooled + outstanding);
+        }
+        Fake::run(w, b);
+        std::lock_guard<std::mutex> lk(mu);
+        running_bytes -= work_per * b.reqs.size();
+        pooled += work_per * b.reqs.size();  // the workspace goes back to the pool
+    }
+    void release(Req &r) override {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            outstanding -= result_per;
+        }
+        Fake::release(r);
+    }
+};
+
+static void test_idle_bytes_charged_and_trimmed() {
+    Pooling f;
+    f.sleep_ms = 2;
+    Core c(&f, 400, 3);  // 3 single queries of 110 fit; a pool of 300 idle bytes must be trimmed to admit more
+    std::vector<int64_t> t;
+    for (int i = 0; i < 40; i++) t.push_back(c.submit(i % 4, 1, i));  // SSSP: one per batch
+    for (auto x : t) {
+        Req r;
+        CHECK(c.wait(x, 10.0, r));
+        CHECK(r.status == 0);
+        CHECK(c.collect(x));
+    }
+    const Stats s = c.stats();
+    CHECK(s.bytes_peak <= 400);
+    CHECK(f.held_peak <= 400);
+    CHECK(s.trims > 0 && f.trims.load() > 0);
+    CHECK(s.bytes_idle == f.idle_bytes());
+    std::puts("ok idle bytes");
+}
+
 int main() {
     test_admission();
     test_batching_and_results();
@@ -153,6 +217,7 @@ int main() {
     test_uncollected_results_hold_memory();
     test_failed_query_frees_memory();
     test_concurrent_workers_overlap();
+    test_idle_bytes_charged_and_trimmed();
     std::puts("ALL OK");
     return 0;
 }
