@@ -76,6 +76,8 @@ def parse():
     p.add_argument("--tune", action="store_true",
                    help="also run the autotuner per algorithm on R-MAT 22 and report its picks beside the step's schedules")
     p.add_argument("--tune-budget-s", type=float, default=8.0, help="autotuner wall-clock budget per algorithm")
+    p.add_argument("--pr-segment", type=int, default=PR_SEGMENT,
+                   help="PageRank pull EdgeBlocking segment width (source vertices per segment)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy three times (scales rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     return p.parse_args()
@@ -85,14 +87,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def schedules(gg):
+def schedules(gg, pr_segment=PR_SEGMENT):
     """The schedule each algorithm runs in the step (chosen by sweeps on this graph family)."""
     bfs = gg.schedule_preset(gg.ALGO_BFS, gg.PRESET_POWERLAW)
     bfs.s1.load_balance = gg.LB_STRICT
     bfs.threshold = 0.01
     sssp = gg.make_schedule(lb="strict", delta=4096)
     cc = gg.make_schedule(lb="edge_only")
-    pr = gg.make_schedule(lb="strict", direction=gg.PULL, edge_blocking=True, blocking_size=PR_SEGMENT)
+    pr = gg.make_schedule(lb="strict", direction=gg.PULL, edge_blocking=True, blocking_size=pr_segment)
     bc = gg.schedule_preset(gg.ALGO_BC, gg.PRESET_POWERLAW)
     bc.s1.load_balance = gg.LB_STRICT
     bc.threshold = 0.01
@@ -182,12 +184,12 @@ def main():
         (args.scale, g.n, g.m, time.time() - t0, src, deg[src]))
     G = gg.Graph.from_graphgen(g)
     torch.cuda.synchronize()
-    scheds = schedules(gg)
+    scheds = schedules(gg, args.pr_segment)
     # PageRank's EdgeBlocking layout, built once per graph outside the timed step
     # (the paper reports this preprocessing separately)
-    pr_eb_ms = G.prepare_pull_blocking(PR_SEGMENT) if (not args.only or "pr" in args.only.split(",")) else None
+    pr_eb_ms = G.prepare_pull_blocking(args.pr_segment) if (not args.only or "pr" in args.only.split(",")) else None
     if pr_eb_ms is not None:
-        log("PageRank pull EdgeBlocking layout (N = %d) built in %.2f ms" % (PR_SEGMENT, pr_eb_ms))
+        log("PageRank pull EdgeBlocking layout (N = %d) built in %.2f ms" % (args.pr_segment, pr_eb_ms))
     algos = [a for a in ["bfs", "sssp", "cc", "pr", "bc"] if not args.only or a in args.only.split(",")]
     stream = torch.cuda.current_stream()
 
@@ -327,7 +329,7 @@ def main():
         # edges, one fp64 accumulator read and written. A launch covers one
         # segment, so a round's bytes are spread over its launches.
         m = g.m
-        seg = g.col // PR_SEGMENT
+        seg = g.col // args.pr_segment
         chg = np.empty(m, dtype=bool)
         chg[0] = True
         chg[1:] = seg[1:] != seg[:-1]
@@ -338,7 +340,7 @@ def main():
         alg_bytes = (8.0 * m + 16.0 * pairs) / launches_per_round
         achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9
         traffic = measured_traffic("paper_2012_07990_amd/csrc/pr.hip", "k_pr_strict_chunks_rmat22.md",
-                                   "PULL+STRICT+EB(%d)+LDS(%d)" % (PR_SEGMENT, PR_LDS_SOURCES))
+                                   "PULL+STRICT+EB(%d)+LDS(%d)" % (args.pr_segment, PR_LDS_SOURCES))
         # the same rounds with every source gathered from global memory
         st0 = gg.Stats()
         st0.flags = gg.STATS_TIME_KERNELS
@@ -785,6 +787,11 @@ def host_cpu():
     return model, avail
 
 
+def gg_lb_edge_only():
+    import paper_2012_07990_amd as gg
+    return gg.LB_EDGE_ONLY
+
+
 def algorithmic_bytes(algo, g, depth, sched, st):
     """Bytes the method itself must move for one run (the per-vertex and
     per-edge figures of the byte model in the design doc), from the run's device
@@ -799,6 +806,11 @@ def algorithmic_bytes(algo, g, depth, sched, st):
     if algo == "sssp":
         return 20.0 * V + 12.0 * E
     if algo == "cc":
+        if sched.s1.load_balance == gg_lb_edge_only():
+            # EDGE_ONLY sweeps every undirected edge once as a (u, v) pair:
+            # 8 bytes of pair plus the two labels per pair, and per vertex the
+            # shortcut's label read and write
+            return 8.0 * V + 16.0 * E
         return 12.0 * V + 8.0 * E
     if algo == "pr":
         return 20.0 * (16.0 * n + 8.0 * m)

@@ -58,8 +58,9 @@ def _ptr(a: np.ndarray):
 
 @dataclass
 class Graph:
-    """Symmetric CSR: row_ptr int32[n+1], col int32[m] (rows sorted, unique,
-    no self-loops), optional symmetric uint32 weights w[m]."""
+    """CSR: row_ptr int32[n+1], col int32[m] (rows sorted, unique, no
+    self-loops), optional uint32 weights w[m]. Symmetric unless built by a
+    *directed* generator, whose rows are out-edges."""
     n: int
     row_ptr: np.ndarray
     col: np.ndarray
@@ -122,6 +123,47 @@ def rmat(scale: int, ef: int = 16, a: float = 0.57, b: float = 0.19, c: float = 
     if weights:
         add_weights(g, seed + 7 if weight_seed is None else weight_seed)
     return g
+
+
+def from_edges_directed(n: int, src, dst, name: str = "") -> Graph:
+    """Directed CSR (rows are out-edges) from an edge list: self-loops
+    dropped, repeated edges merged, rows sorted; not symmetrised."""
+    src = np.asarray(src, dtype=np.int64)
+    dst = np.asarray(dst, dtype=np.int64)
+    assert src.shape == dst.shape
+    if src.size:
+        assert src.min() >= 0 and dst.min() >= 0 and src.max() < n and dst.max() < n
+    keep = src != dst
+    key = np.unique(src[keep] * n + dst[keep])
+    s = key // n
+    col = (key % n).astype(np.int32)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(s, minlength=n), out=row_ptr[1:])
+    return Graph(n, row_ptr.astype(np.int32), col, None, name)
+
+
+def rmat_directed(scale: int, ef: int = 16, a: float = 0.57, b: float = 0.19, c: float = 0.19,
+                  seed: Optional[int] = None, weights: bool = False,
+                  weight_seed: Optional[int] = None) -> Graph:
+    """The R-MAT(scale, ef, a, b, c) edge list of rmat() kept directed: each
+    generated edge u -> v once, no mirror."""
+    if seed is None:
+        seed = 1000 + scale
+    src, dst = rmat_edges(scale, ef, a, b, c, seed)
+    g = from_edges_directed(1 << scale, src, dst, name="rmat%d-directed" % scale)
+    del src, dst
+    if weights:
+        add_weights(g, seed + 7 if weight_seed is None else weight_seed)
+    return g
+
+
+def random_digraph(n: int, p: float, seed: int) -> Graph:
+    """Directed G(n, p): each ordered pair u != v kept with probability p
+    (counter-based stream)."""
+    u, v = np.nonzero(~np.eye(n, dtype=bool))
+    keep = np.array([rng(seed, int(i)) >> 11 for i in range(u.size)], dtype=np.float64) \
+        * (1.0 / 9007199254740992.0) < p
+    return from_edges_directed(n, u[keep], v[keep], name="dgnp%d" % n)
 
 
 def add_weights(g: Graph, seed: int, wmax: int = 999) -> Graph:

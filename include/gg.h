@@ -142,7 +142,10 @@ typedef struct gg_graph gg_graph;
 #define GG_VALIDATE 2u     /* O(m) check: row_ptr[0]=0, monotone, row_ptr[n]=m,
                               0<=col<n, rows strictly ascending, no self-loops */
 #define GG_SYMMETRIC 4u    /* caller asserts (u,v) in E <=> (v,u) in E; required by
-                              PULL and by the undirected algorithms (CC, BC, PR) */
+                              CC, the batched BFS/BC forms and serving. Without it
+                              the CSR rows are out-edges: PULL steps read the
+                              graph's transpose (in-rows, sources ascending), built
+                              on the host once, on first use */
 
 /*
  * Build a device-resident CSR graph (the `load` of the paper's BFS program).
@@ -173,12 +176,12 @@ gg_status gg_graph_prepare_edgeblocking(gg_graph *g, int32_t seg_vertices, gg_st
 /*
  * PULL EdgeBlocking layout (not in the paper; the gather-side counterpart of
  * the paper's EdgeBlocking, used by PageRank PULL + STRICT with
- * edge_blocking set): the CSR split by source segment [s*seg_vertices,
+ * edge_blocking set): the in-edge CSR (the graph's own when symmetric, else
+ * its transpose) split by source segment [s*seg_vertices,
  * (s+1)*seg_vertices) into S segment CSRs (rows keep their order) plus the
  * STRICT chunk-to-row partition of each. Owned by the graph, cached per
  * seg_vertices (a later gg_pagerank with that width reuses it). prep_ms (may
  * be NULL) receives the build time on the device (0 when it was cached).
- * Requires GG_SYMMETRIC.
  */
 gg_status gg_graph_prepare_pull_blocking(gg_graph *g, int32_t seg_vertices, gg_stream_t stream, double *prep_ms);
 /*
@@ -224,13 +227,16 @@ gg_status gg_cc(gg_graph *g, const gg_schedule *s, int32_t *label_dev, gg_stream
    The results are bit-identical either way (same values, same order). */
 #define GG_PR_NO_LDS_CACHE 2u
 /* PageRank, fp32: `iters` power-iteration rounds from 1/n with damping
-   `damping`; zero-degree mass spread uniformly unless GG_PR_NO_DANGLING.
-   rank_dev[n] float. Requires GG_SYMMETRIC. */
+   `damping`: rank'(v) = (1-d)/n + d * (sum over in-neighbours u of
+   rank(u)/outdeg(u) + D/n), D = the rank of vertices without out-edges
+   (dropped with GG_PR_NO_DANGLING). rank_dev[n] float. Directed graphs:
+   PULL sums over the transpose, PUSH scatters along out-edges. */
 gg_status gg_pagerank(gg_graph *g, const gg_schedule *s, float damping, int32_t iters,
                       uint32_t flags, float *rank_dev, gg_stream_t stream, gg_stats *stats);
 /* Single-source Brandes betweenness: sigma_dev[n] uint64 shortest-path
    counts, delta_dev[n] float dependencies (delta[src] = 0). GG_ERR_OVERFLOW
-   when a path count would exceed 2^64-1. Requires GG_SYMMETRIC. */
+   when a path count would exceed 2^64-1. Directed graphs: shortest paths
+   follow out-edges (PULL forward steps read the transpose). */
 gg_status gg_bc(gg_graph *g, int32_t src, const gg_schedule *s, uint64_t *sigma_dev,
                 float *delta_dev, gg_stream_t stream, gg_stats *stats);
 

@@ -62,6 +62,10 @@ def _get():
         L.oracle_pagerank.argtypes = [i64, P, P, f64, ctypes.c_int, ctypes.c_int, P]
         L.oracle_bc.restype = ctypes.c_int
         L.oracle_bc.argtypes = [i64, P, P, i32, P, P]
+        L.oracle_check_digraph.restype = ctypes.c_int
+        L.oracle_check_digraph.argtypes = [i64, P, P]
+        L.oracle_pagerank_directed.restype = None
+        L.oracle_pagerank_directed.argtypes = [i64, P, P, f64, ctypes.c_int, ctypes.c_int, P]
         L.oracle_edgeblock.restype = i64
         L.oracle_edgeblock.argtypes = [i64, i64, P, P, i64, P, P, P]
         _lib = L
@@ -84,6 +88,13 @@ def check_csr(n, row_ptr, col) -> int:
     """0 when the CSR is sorted, unique, in range, loop-free and symmetric."""
     rp, c = _csr(row_ptr, col)
     return int(_get().oracle_check_csr(n, _p(rp), _p(c)))
+
+
+def check_digraph(n, row_ptr, col) -> int:
+    """0 when the CSR is sorted, unique, in range and loop-free (directed:
+    no symmetry required); else check_csr's code for the first violation."""
+    rp, c = _csr(row_ptr, col)
+    return int(_get().oracle_check_digraph(n, _p(rp), _p(c)))
 
 
 def bfs(n, row_ptr, col, src) -> np.ndarray:
@@ -124,6 +135,16 @@ def pagerank(n, row_ptr, col, damping=0.85, iters=20, dangling=True) -> np.ndarr
     out = np.empty(max(n, 1), dtype=np.float64)
     _get().oracle_pagerank(n, _p(rp), _p(c), float(damping), int(iters),
                            0 if dangling else 1, _p(out))
+    return out[:n]
+
+
+def pagerank_directed(n, row_ptr, col, damping=0.85, iters=20, dangling=True) -> np.ndarray:
+    """fp64 ranks on a directed graph (rows are out-edges): each vertex
+    passes rank/out-degree along its out-edges; exactly `iters` steps from 1/n."""
+    rp, c = _csr(row_ptr, col)
+    out = np.empty(max(n, 1), dtype=np.float64)
+    _get().oracle_pagerank_directed(n, _p(rp), _p(c), float(damping), int(iters),
+                                    0 if dangling else 1, _p(out))
     return out[:n]
 
 

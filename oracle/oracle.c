@@ -26,6 +26,10 @@
  *   BC     Brandes: BFS path counts sigma (uint64, checked), dependencies
  *          delta[v] = sum over neighbours w one level deeper of
  *          sigma[v]/sigma[w] * (1 + delta[w]), in neighbour order; delta[s]=0.
+ *   Directed graphs (rows are out-edges): BFS, SSSP and BC above follow
+ *          out-edges as written. PR on a directed graph is its own function:
+ *          every vertex passes rank/out-degree along each out-edge, and the
+ *          vertices without out-edges are the dangling ones.
  *   EB     EdgeBlocking preprocessing (the Algorithm for preprocessing the
  *          input graph, GPU-Specific Optimizations section): count edges per
  *          destination segment floor(dst/N), exclusive prefix sum, stable
@@ -56,6 +60,21 @@ int oracle_check_csr(int64_t n, const int32_t *rp, const int32_t *col) {
                 if (col[mid] < v) lo = mid + 1; else hi = mid;
             }
             if (lo >= rp[u + 1] || col[lo] != v) return 6;
+        }
+    }
+    return 0;
+}
+
+/* ---- CSR sanity for a directed graph: sorted, unique, in range, no
+   self-loops (no symmetry). Same codes as oracle_check_csr. ---------------- */
+int oracle_check_digraph(int64_t n, const int32_t *rp, const int32_t *col) {
+    if (n < 0 || rp[0] != 0) return 1;
+    for (int64_t v = 0; v < n; v++) {
+        if (rp[v + 1] < rp[v]) return 2;
+        for (int64_t e = rp[v]; e < rp[v + 1]; e++) {
+            if (col[e] < 0 || col[e] >= n) return 3;
+            if (col[e] == v) return 4;
+            if (e > rp[v] && col[e] <= col[e - 1]) return 5;
         }
     }
     return 0;
@@ -190,6 +209,30 @@ void oracle_pagerank(int64_t n, const int32_t *rp, const int32_t *col, double da
         memcpy(rank, next, sizeof(double) * (size_t)n);
     }
     free(next);
+}
+
+/* ---- PageRank on a directed graph ----------------------------------------------
+   next[v] = (1-d)/n + d * (sum over edges u -> v of rank[u]/outdeg(u) + D/n),
+   D = the rank held by vertices with no out-edge (variant 0) or 0 (variant 1). */
+void oracle_pagerank_directed(int64_t n, const int32_t *rp, const int32_t *col, double damping,
+                              int iters, int variant, double *rank) {
+    double *in_sum = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int64_t v = 0; v < n; v++) rank[v] = 1.0 / (double)n;
+    for (int t = 0; t < iters; t++) {
+        double dangling = 0.0;
+        for (int64_t v = 0; v < n; v++) in_sum[v] = 0.0;
+        for (int64_t u = 0; u < n; u++) {
+            int64_t outdeg = rp[u + 1] - rp[u];
+            if (outdeg == 0) {
+                if (variant == 0) dangling += rank[u];
+                continue;
+            }
+            for (int64_t e = rp[u]; e < rp[u + 1]; e++) in_sum[col[e]] += rank[u] / (double)outdeg;
+        }
+        for (int64_t v = 0; v < n; v++)
+            rank[v] = (1.0 - damping) / (double)n + damping * (in_sum[v] + dangling / (double)n);
+    }
+    free(in_sum);
 }
 
 /* ---- betweenness (single source) -------------------------------------------- */

@@ -266,6 +266,7 @@ def gg_bfs(graph, src, sched, depth, stream=None, stats=None):
                        _stats_ptr(stats)), "gg_bfs")
 
 
+
 def gg_sssp(graph, src, sched, dist, stream=None, stats=None):
     _check(_lib.gg_sssp(graph.handle, int(src), _sched_ptr(sched), _dptr(dist), _stream(stream),
                         _stats_ptr(stats)), "gg_sssp")

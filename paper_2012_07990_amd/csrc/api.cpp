@@ -76,7 +76,7 @@ size_t Graph::pooled_bytes() {
 
 size_t Graph::layout_bytes() {
     std::lock_guard<std::mutex> lk(mu);
-    size_t b = coo_src.bytes();
+    size_t b = coo_src.bytes() + upper.bytes() + in_rp.bytes() + in_col.bytes();
     for (auto &kv : eb) b += kv.second->src.bytes() + kv.second->dst.bytes();
     for (auto &kv : pull_eb) {
         const PullBlocked &p = *kv.second;
@@ -227,7 +227,6 @@ gg_status gg_graph_prepare_pull_blocking(gg_graph *g, int32_t seg_vertices, gg_s
     return guarded([&] {
         check_graph(g);
         require(seg_vertices >= 1, GG_ERR_INVALID_ARG, "seg_vertices must be >= 1");
-        require(g->g.symmetric, GG_ERR_INVALID_ARG, "PULL needs a symmetric graph (GG_SYMMETRIC)");
         const double ms = pull_layout_prepare(g->g, seg_vertices, S(stream));
         if (prep_ms) *prep_ms = ms;
     });
@@ -321,7 +320,6 @@ gg_status gg_pagerank(gg_graph *g, const gg_schedule *s, float damping, int32_t 
         require((flags & ~(GG_PR_NO_DANGLING | GG_PR_NO_LDS_CACHE)) == 0, GG_ERR_INVALID_ARG,
                 "unknown PageRank flags");
         require(damping >= 0.f && damping <= 1.f, GG_ERR_INVALID_ARG, "damping must be in [0, 1]");
-        require(g->g.symmetric, GG_ERR_INVALID_ARG, "PageRank needs a symmetric graph (GG_SYMMETRIC)");
         const gg_schedule sc = s ? *s : default_schedule();
         validate_schedule(g->g, GG_ALGO_PR, sc);
         pr_run(g->g, sc, damping, iters, flags, rank_dev, S(stream), stats);
@@ -334,7 +332,6 @@ gg_status gg_bc(gg_graph *g, int32_t src, const gg_schedule *s, uint64_t *sigma_
         check_graph(g);
         require(src >= 0 && src < g->g.n, GG_ERR_INVALID_ARG, "source out of range");
         require(sigma_dev && delta_dev, GG_ERR_INVALID_ARG, "sigma/delta is NULL");
-        require(g->g.symmetric, GG_ERR_INVALID_ARG, "BC needs a symmetric graph (GG_SYMMETRIC)");
         const gg_schedule sc = s ? *s : default_schedule();
         validate_schedule(g->g, GG_ALGO_BC, sc);
         bc_run(g->g, src, sc, sigma_dev, delta_dev, S(stream), stats);
@@ -390,8 +387,8 @@ gg_status gg_autotune(gg_graph *g, int32_t algo, double budget_s, const int32_t 
         require(out != nullptr, GG_ERR_INVALID_ARG, "out is NULL");
         require(algo >= GG_ALGO_BFS && algo <= GG_ALGO_BC, GG_ERR_INVALID_ARG, "unknown algorithm");
         require(nprobe >= 0 && (nprobe == 0 || probe_srcs), GG_ERR_INVALID_ARG, "bad probe sources");
-        if (algo == GG_ALGO_CC || algo == GG_ALGO_PR || algo == GG_ALGO_BC)
-            require(g->g.symmetric, GG_ERR_INVALID_ARG, "this algorithm needs a symmetric graph (GG_SYMMETRIC)");
+        if (algo == GG_ALGO_CC)
+            require(g->g.symmetric, GG_ERR_INVALID_ARG, "CC needs a symmetric graph (GG_SYMMETRIC)");
         *out = autotune(g->g, algo, budget_s, probe_srcs, nprobe, S(stream), best_ms);
     });
 }

@@ -95,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void k_bc_pull(DevGraph g, int32_t *depth, 
         __syncthreads();
         const int v = base + tid;
         if (v < g.n && depth[v] < 0) {
-            const int beg = g.row_ptr[v], end = g.row_ptr[v + 1];
+            const int beg = g.in_row_ptr[v], end = g.in_row_ptr[v + 1];
             const int deg = end - beg;
             if (deg < kWave) {
                 unsigned long long s = 0;
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_bc_pull(DevGraph g, int32_t *depth, 
                     bool in[kEdgeBatch];
                     unsigned long long su[kEdgeBatch];
 #pragma unroll
-                    for (int b = 0; b < kEdgeBatch; b++) uu[b] = g.col[e0 + b < end ? e0 + b : end - 1];
+                    for (int b = 0; b < kEdgeBatch; b++) uu[b] = g.in_col[e0 + b < end ? e0 + b : end - 1];
 #pragma unroll
                     for (int b = 0; b < kEdgeBatch; b++) in[b] = e0 + b < end && member(uu[b]);
 #pragma unroll
@@ -133,8 +133,8 @@ __global__ __launch_bounds__(kBlock) void k_bc_pull(DevGraph g, int32_t *depth, 
             unsigned long long s = 0;
             int any = 0;
             bool wrap = false;
-            for (int e = g.row_ptr[vv] + lane; e < g.row_ptr[vv + 1]; e += kWave) {
-                const int u = g.col[e];
+            for (int e = g.in_row_ptr[vv] + lane; e < g.in_row_ptr[vv + 1]; e += kWave) {
+                const int u = g.in_col[e];
                 ne++;
                 if (member(u)) {
                     const unsigned long long su = sigma[u];
@@ -153,8 +153,8 @@ __global__ __launch_bounds__(kBlock) void k_bc_pull(DevGraph g, int32_t *depth, 
             unsigned long long s = 0;
             int any = 0;
             bool wrap = false;
-            for (int e = g.row_ptr[vv] + tid; e < g.row_ptr[vv + 1]; e += kBlock) {
-                const int u = g.col[e];
+            for (int e = g.in_row_ptr[vv] + tid; e < g.in_row_ptr[vv + 1]; e += kBlock) {
+                const int u = g.in_col[e];
                 ne++;
                 if (member(u)) {
                     const unsigned long long su = sigma[u];
@@ -301,6 +301,7 @@ void bc_run(Graph &G, int32_t src, const gg_schedule &sch, uint64_t *sigma_out, 
     Lease ws(G);
     if (sch.s1.load_balance == GG_LB_EDGE_ONLY || (sch.hybrid && sch.s2.load_balance == GG_LB_EDGE_ONLY))
         ensure_coo(c, G);
+    if (schedule_pulls(sch)) ensure_transpose(c, G);  // directed graphs: PULL sums over in-edges
     const DevGraph g = G.view();
     const int n = g.n;
     unsigned long long *sigma = reinterpret_cast<unsigned long long *>(sigma_out);

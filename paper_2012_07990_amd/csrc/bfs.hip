@@ -36,14 +36,15 @@ __device__ __forceinline__ void bfs_pull_dev(const DevGraph &g, int32_t *depth, 
         const int v = (int)v0;
         bool found = false;
         if (v < g.n && depth[v] < 0) {
-            const int end = g.row_ptr[v + 1];
-            // parents probed kEdgeBatch at a time (their loads overlap); stop at
-            // the first parent in the input frontier, counting edges up to it
-            for (int e0 = g.row_ptr[v]; e0 < end && !found; e0 += kEdgeBatch) {
+            const int end = g.in_row_ptr[v + 1];
+            // parents (in-neighbours) probed kEdgeBatch at a time (their loads
+            // overlap); stop at the first parent in the input frontier,
+            // counting edges up to it
+            for (int e0 = g.in_row_ptr[v]; e0 < end && !found; e0 += kEdgeBatch) {
                 int uu[kEdgeBatch];
                 bool in[kEdgeBatch];
 #pragma unroll
-                for (int b = 0; b < kEdgeBatch; b++) uu[b] = g.col[e0 + b < end ? e0 + b : end - 1];
+                for (int b = 0; b < kEdgeBatch; b++) uu[b] = g.in_col[e0 + b < end ? e0 + b : end - 1];
 #pragma unroll
                 for (int b = 0; b < kEdgeBatch; b++)
                     in[b] = IN_REP == kRepBoolmap ? (in_bool[uu[b]] != 0) : bit_test(in_bits, uu[b]);
@@ -244,13 +245,20 @@ void bfs_pull_step(Ctx &c, const DevGraph &g, FrontierState &fs, const gg_simple
 }
 
 void bfs_run(Graph &G, int32_t src, const gg_schedule &s, int32_t *depth, hipStream_t stream, gg_stats *st) {
+    Lease ws(G);
+    bfs_run_ws(G, *ws, src, s, depth, stream, st);
+}
+
+void bfs_run_ws(Graph &G, Workspace &wsr, int32_t src, const gg_schedule &s, int32_t *depth, hipStream_t stream,
+                gg_stats *st) {
     Ctx c;
     c.s = stream;
     c.num_cus = G.num_cus;
     StatsScope scope(st, c);
-    Lease ws(G);
+    Workspace *ws = &wsr;
     if (s.s1.load_balance == GG_LB_EDGE_ONLY || (s.hybrid && s.s2.load_balance == GG_LB_EDGE_ONLY))
         ensure_coo(c, G);
+    if (schedule_pulls(s)) ensure_transpose(c, G);  // directed graphs: PULL reads in-edges
     const DevGraph g = G.view();
     if (s.s1.kernel_fusion) {
         bfs_fused(c, G, *ws, src, s, depth, st);

@@ -6,6 +6,8 @@
 // it reaches (shortcutting). Rounds repeat until a sweep hooks nothing. Labels
 // only decrease and never leave the component, so the fixpoint labels every
 // vertex with the smallest id of its component.
+#include <algorithm>
+
 #include "algos.hpp"
 #include "driver.hpp"
 #include "fused.hpp"
@@ -48,6 +50,91 @@ struct CcHook {
     __device__ __forceinline__ void begin() const {}
     __device__ __forceinline__ void flush() const {}
 };
+
+// EDGE_ONLY on a symmetric graph: every undirected edge once, as the pairs
+// (u, v) with u < v (the hook ignores the mirrored entries anyway), each lane
+// loading kEdgeBatch pairs and their labels before hooking any of them
+__global__ __launch_bounds__(kBlock) void k_cc_hook_pairs(const int2 *pairs, long long np, CcHook f,
+                                                          unsigned long long *ecount) {
+    const long long stride = (long long)gridDim.x * kBlock;
+    long long ne = 0;
+    for (long long e0 = (long long)blockIdx.x * kBlock + threadIdx.x; e0 < np; e0 += kEdgeBatch * stride) {
+        int2 pp[kEdgeBatch];
+        CcHook::Pre pre[kEdgeBatch];
+#pragma unroll
+        for (int b = 0; b < kEdgeBatch; b++) {
+            const long long e = e0 + b * stride;
+            // one 8-byte non-temporal load per pair (x in the low word)
+            const unsigned long long w = __builtin_nontemporal_load(
+                reinterpret_cast<const unsigned long long *>(pairs) + (e < np ? e : np - 1));
+            pp[b] = make_int2((int)(unsigned)w, (int)(unsigned)(w >> 32));
+        }
+#pragma unroll
+        for (int b = 0; b < kEdgeBatch; b++) pre[b] = f.load(pp[b].x, pp[b].y, 0);
+#pragma unroll
+        for (int b = 0; b < kEdgeBatch; b++) {
+            const bool live = e0 + b * stride < np;
+            // a lane past the end repeats the last pair: the hook is idempotent
+            f.apply(pp[b].x, pp[b].y, 0, pre[b]);
+            ne += live;
+        }
+    }
+    flush_edge_count(ne, ecount);
+}
+
+// per vertex: the number of its neighbours above it (rows are sorted)
+__global__ __launch_bounds__(kBlock) void k_upper_count(const int32_t *rp, const int32_t *col, int n, int32_t *cnt) {
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
+        int lo = rp[v], hi = rp[v + 1];
+        const int end = hi;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (col[mid] <= v) lo = mid + 1; else hi = mid;
+        }
+        cnt[v] = end - lo;
+    }
+}
+
+// one wavefront per vertex copies its upper neighbours as pairs
+__global__ __launch_bounds__(kBlock) void k_upper_fill(const int32_t *rp, const int32_t *col, int n,
+                                                      const int32_t *off, int2 *pairs) {
+    const int wpb = kBlock / kWave;
+    for (int v = blockIdx.x * wpb + threadIdx.x / kWave; v < n; v += gridDim.x * wpb) {
+        const int end = rp[v + 1], cntv = off[v + 1] - off[v];
+        const int first = end - cntv;
+        for (int i = lane_id(); i < cntv; i += kWave) pairs[off[v] + i] = make_int2(v, col[first + i]);
+    }
+}
+
+// Built once per graph under its lock and completed before the lock is
+// released (a query on another stream that finds it present reads a
+// finished list).
+static void ensure_upper(Ctx &c, Graph &G) {
+    std::lock_guard<std::mutex> lk(G.mu);
+    if (G.upper.p) return;
+    const int n = G.n;
+    DevBuf<int32_t> off;
+    DevBuf<long long> part;
+    off.ensure((size_t)n + 1);
+    part.ensure(exclusive_scan_partials(n));
+    hipLaunchKernelGGL(k_upper_count, dim3(blocks_for(n, kBlock, 8192)), dim3(kBlock), 0, c.s, G.row_ptr.p,
+                       G.col.p, n, off.p);
+    GG_CHECK_LAUNCH();
+    exclusive_scan_i32(c, off.p, n, part.p);
+    int32_t total = 0;
+    GG_HIP(hipMemcpyAsync(&total, off.p + n, sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
+    GG_HIP(hipStreamSynchronize(c.s));
+    DevBuf<int2> pairs;
+    pairs.ensure((size_t)std::max(total, 1));
+    hipLaunchKernelGGL(k_upper_fill, dim3(blocks_for(n, kBlock / kWave, 16384)), dim3(kBlock), 0, c.s,
+                       G.row_ptr.p, G.col.p, n, off.p, pairs.p);
+    GG_CHECK_LAUNCH();
+    GG_HIP(hipStreamSynchronize(c.s));
+    c.launches += 3;
+    G.m_upper = total;
+    std::swap(G.upper.p, pairs.p);
+    std::swap(G.upper.n, pairs.n);
+}
 
 __global__ __launch_bounds__(kBlock) void k_cc_init(int32_t *label, int32_t *ids, int n) {
     for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
@@ -118,7 +205,7 @@ void cc_run(Graph &G, const gg_schedule &sch, int32_t *label, hipStream_t stream
     StatsScope scope(st, c);
     Lease ws(G);
     const gg_simple_schedule &s = sch.s1;
-    if (s.load_balance == GG_LB_EDGE_ONLY) ensure_coo(c, G);
+    if (s.load_balance == GG_LB_EDGE_ONLY && !G.symmetric) ensure_coo(c, G);
     const DevGraph g = G.view();
     const int n = g.n;
     ws->aux_i32[0].ensure(n);  // identity frontier: every vertex is a source each round
@@ -147,6 +234,27 @@ void cc_run(Graph &G, const gg_schedule &sch, int32_t *label, hipStream_t stream
             st->fused = 1;
             st->iterations = read_i32(c, ws->counters.p + 3, ws->h_i32.p);
             st->push_iterations = st->iterations;
+        }
+        scope.finish();
+        return;
+    }
+    if (s.load_balance == GG_LB_EDGE_ONLY && G.symmetric) {
+        ensure_upper(c, G);
+        const long long np = G.m_upper;
+        for (;;) {
+            fill_i32(c, ws->counters.p, 1, 0);
+            if (np > 0) {
+                hipLaunchKernelGGL(k_cc_hook_pairs, dim3(blocks_for((np + kEdgeBatch - 1) / kEdgeBatch, kBlock, 16384)),
+                                   dim3(kBlock), 0, c.s, G.upper.p, np, CcHook{label, ws->counters.p},
+                                   c.edge_counter);
+                GG_CHECK_LAUNCH();
+                c.launches++;
+            }
+            hipLaunchKernelGGL(k_cc_compress, dim3(blocks_for(n, kBlock, 8192)), dim3(kBlock), 0, c.s, label, n);
+            GG_CHECK_LAUNCH();
+            c.launches++;
+            if (st) { st->iterations++; st->push_iterations++; st->vertices_processed += n; }
+            if (read_i32(c, ws->counters.p, ws->h_i32.p) == 0) break;
         }
         scope.finish();
         return;

@@ -45,6 +45,10 @@ struct DevGraph {
     const int32_t *__restrict__ col;      // [m]
     const uint32_t *__restrict__ w;       // [m] or null
     const int32_t *__restrict__ coo_src;  // [m] source of each CSR entry (EDGE_ONLY) or null
+    // in-edges for PULL: the CSR itself on a symmetric graph, else its
+    // transpose (in-rows sorted by source; null until built)
+    const int32_t *__restrict__ in_row_ptr;
+    const int32_t *__restrict__ in_col;
 };
 
 // ---- wavefront helpers -----------------------------------------------------------

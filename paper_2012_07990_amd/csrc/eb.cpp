@@ -62,4 +62,38 @@ double edgeblock_prepare(Ctx &c, Graph &G, int32_t N) {
     return ms;
 }
 
+// In-edges of a directed graph for PULL traversals (the configDirection
+// PULL choice reads the sources of each destination): the transpose of the
+// CSR by a stable counting sort over destinations, so each in-row keeps its
+// sources ascending. Runs once per graph on the host, like the preprocessing
+// above; the transpose is uploaded and owned by the graph, published only
+// once complete. Symmetric graphs read their own CSR.
+void ensure_transpose(Ctx &c, Graph &G) {
+    if (G.symmetric) return;
+    std::lock_guard<std::mutex> lk(G.mu);
+    if (G.in_rp.p) return;
+    const int32_t n = G.n;
+    const int64_t m = G.m;
+    std::vector<int32_t> rp((size_t)n + 1), col((size_t)m);
+    GG_HIP(hipMemcpyAsync(rp.data(), G.row_ptr.p, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, c.s));
+    if (m) GG_HIP(hipMemcpyAsync(col.data(), G.col.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost, c.s));
+    GG_HIP(hipStreamSynchronize(c.s));
+    std::vector<int32_t> irp((size_t)n + 1, 0), icol((size_t)(m > 0 ? m : 1));
+    for (int64_t e = 0; e < m; e++) irp[(size_t)col[e] + 1]++;
+    for (int32_t v = 0; v < n; v++) irp[(size_t)v + 1] += irp[v];
+    std::vector<int32_t> cursor(irp.begin(), irp.end() - 1);
+    for (int32_t u = 0; u < n; u++)
+        for (int64_t e = rp[u]; e < rp[u + 1]; e++) icol[(size_t)cursor[col[e]]++] = u;
+    DevBuf<int32_t> drp, dcol;
+    drp.ensure((size_t)n + 1);
+    dcol.ensure((size_t)(m > 0 ? m : 1));
+    GG_HIP(hipMemcpyAsync(drp.p, irp.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, c.s));
+    if (m) GG_HIP(hipMemcpyAsync(dcol.p, icol.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, c.s));
+    GG_HIP(hipStreamSynchronize(c.s));
+    std::swap(G.in_rp.p, drp.p);
+    std::swap(G.in_rp.n, drp.n);
+    std::swap(G.in_col.p, dcol.p);
+    std::swap(G.in_col.n, dcol.n);
+}
+
 }  // namespace gg

@@ -43,8 +43,12 @@ struct Tid {  // position of this lane in the (possibly persistent) grid
 };
 
 // ---------------------------------------------------------------------------- VP
-// One lane per frontier vertex walks its edges, loading kEdgeBatch edges at a
-// time; appends are staged per workgroup unless STAGE is false (see lb_cm).
+// One lane per frontier vertex walks its edges, kVpBatch at a time: their
+// column reads, then their functor reads, then their updates are each issued
+// back to back, so a hub's serial walk pays three memory round trips per
+// kVpBatch edges. Appends are staged per workgroup unless STAGE is false
+// (see lb_cm).
+constexpr int kVpBatch = 16;
 template <int CREATE, int DEDUP, bool STAGE = true, class Src, class F>
 __device__ void lb_vp(const DevGraph &g, const Src &src, F &f, const OutFrontier &out, Tid t,
                       long long &ne) {
@@ -60,21 +64,28 @@ __device__ void lb_vp(const DevGraph &g, const Src &src, F &f, const OutFrontier
         const int u = i < src.size ? src.get(i) : 0;
         if (i < src.size && f.active(u)) {
             const int end = g.row_ptr[u + 1];
-            for (int e0 = g.row_ptr[u]; e0 < end && !f.done(u); e0 += kEdgeBatch) {
-                int vv[kEdgeBatch];
-                typename F::Pre pp[kEdgeBatch];
+            for (int e0 = g.row_ptr[u]; e0 < end && !f.done(u); e0 += kVpBatch) {
+                int vv[kVpBatch];
+                typename F::Pre pp[kVpBatch];
 #pragma unroll
-                for (int b = 0; b < kEdgeBatch; b++) vv[b] = g.col[e0 + b < end ? e0 + b : end - 1];
+                for (int b = 0; b < kVpBatch; b++) vv[b] = g.col[e0 + b < end ? e0 + b : end - 1];
 #pragma unroll
-                for (int b = 0; b < kEdgeBatch; b++) pp[b] = f.load(u, vv[b], e0 + b < end ? e0 + b : end - 1);
+                for (int b = 0; b < kVpBatch; b++) pp[b] = f.load(u, vv[b], e0 + b < end ? e0 + b : end - 1);
+                // every update of the batch (its atomics) is issued before any
+                // result is consumed by an append
+                int xx[kVpBatch];
 #pragma unroll
-                for (int b = 0; b < kEdgeBatch; b++) {
+                for (int b = 0; b < kVpBatch; b++) {
+                    xx[b] = -1;
                     if (e0 + b < end && !f.done(u)) {
-                        const int x = f.apply(u, vv[b], e0 + b, pp[b]);
-                        if constexpr (STAGE) emit_staged<CREATE, DEDUP>(out, s_st, x >= 0, x);
-                        else emit<CREATE, DEDUP>(out, x >= 0, x);
+                        xx[b] = f.apply(u, vv[b], e0 + b, pp[b]);
                         ne++;
                     }
+                }
+#pragma unroll
+                for (int b = 0; b < kVpBatch; b++) {
+                    if constexpr (STAGE) emit_staged<CREATE, DEDUP>(out, s_st, xx[b] >= 0, xx[b]);
+                    else emit<CREATE, DEDUP>(out, xx[b] >= 0, xx[b]);
                 }
             }
         }
@@ -243,14 +254,19 @@ __device__ void lb_etwc(const DevGraph &g, const Src &src, F &f, const OutFronti
                 for (int b = 0; b < kEdgeBatch; b++) vv[b] = g.col[e0 + b < end ? e0 + b : end - 1];
 #pragma unroll
                 for (int b = 0; b < kEdgeBatch; b++) pp[b] = f.load(u, vv[b], e0 + b < end ? e0 + b : end - 1);
+                int xx[kEdgeBatch];
 #pragma unroll
                 for (int b = 0; b < kEdgeBatch; b++) {
+                    xx[b] = -1;
                     if (e0 + b < end && !f.done(u)) {
-                        const int x = f.apply(u, vv[b], e0 + b, pp[b]);
-                        if constexpr (STAGE) emit_staged<CREATE, DEDUP>(out, s_st, x >= 0, x);
-                        else emit<CREATE, DEDUP>(out, x >= 0, x);
+                        xx[b] = f.apply(u, vv[b], e0 + b, pp[b]);
                         ne++;
                     }
+                }
+#pragma unroll
+                for (int b = 0; b < kEdgeBatch; b++) {
+                    if constexpr (STAGE) emit_staged<CREATE, DEDUP>(out, s_st, xx[b] >= 0, xx[b]);
+                    else emit<CREATE, DEDUP>(out, xx[b] >= 0, xx[b]);
                 }
             }
         }
@@ -448,14 +464,17 @@ __device__ void lb_strict(const DevGraph &g, const Src &src, const long long *sc
                 for (int k = 0; k < kEdgeBatch; k++) vv[k] = g.col[ee[k]];
 #pragma unroll
                 for (int k = 0; k < kEdgeBatch; k++) pp[k] = f.load(uu[k], vv[k], ee[k]);
+                int xx[kEdgeBatch];
 #pragma unroll
                 for (int k = 0; k < kEdgeBatch; k++) {
+                    xx[k] = -1;
                     if (rb + (long long)k * kBlock < hi && !f.done(uu[k])) {
-                        const int x = f.apply(uu[k], vv[k], ee[k], pp[k]);
-                        emit_staged<CREATE, DEDUP>(out, s_st, x >= 0, x);
+                        xx[k] = f.apply(uu[k], vv[k], ee[k], pp[k]);
                         ne++;
                     }
                 }
+#pragma unroll
+                for (int k = 0; k < kEdgeBatch; k++) emit_staged<CREATE, DEDUP>(out, s_st, xx[k] >= 0, xx[k]);
             }
             __syncthreads();
             emit_flush<CREATE>(out, s_st);

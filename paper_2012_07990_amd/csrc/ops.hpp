@@ -70,17 +70,28 @@ struct DevBuf {
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
+    bool fixed = false;  // borrowed memory: never freed, never grown
     ~DevBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && !fixed) (void)hipFree(p);
         p = nullptr;
         n = 0;
+        fixed = false;
+    }
+    // use `count` elements at `ptr` (owned elsewhere); a later ensure() past
+    // them throws instead of allocating
+    void borrow(T *ptr, size_t count) {
+        release();
+        p = ptr;
+        n = count;
+        fixed = true;
     }
     // device bytes held
-    size_t bytes() const { return p ? (n ? n : 1) * sizeof(T) : 0; }
+    size_t bytes() const { return p && !fixed ? (n ? n : 1) * sizeof(T) : 0; }
     // grow-only allocation (contents not preserved)
     void ensure(size_t count) {
         if (count <= n && p) return;
+        require(!fixed, GG_ERR_INVALID_ARG, "a borrowed (no-allocation) workspace buffer is too small");
         release();
         size_t bytes = (count ? count : 1) * sizeof(T);
         GG_HIP(hipMalloc(&p, bytes));
@@ -92,13 +103,21 @@ template <class T>
 struct HostPinned {
     T *p = nullptr;
     size_t n = 0;
+    bool fixed = false;  // borrowed host memory (not pinned by this object)
     HostPinned() = default;
     HostPinned(const HostPinned &) = delete;
     ~HostPinned() {
-        if (p) (void)hipHostFree(p);
+        if (p && !fixed) (void)hipHostFree(p);
+    }
+    void borrow(T *ptr, size_t count) {
+        if (p && !fixed) (void)hipHostFree(p);
+        p = ptr;
+        n = count;
+        fixed = true;
     }
     void ensure(size_t count) {
         if (count <= n && p) return;
+        require(!fixed, GG_ERR_INVALID_ARG, "a borrowed (no-allocation) host buffer is too small");
         if (p) (void)hipHostFree(p);
         p = nullptr;
         GG_HIP(hipHostMalloc(&p, (count ? count : 1) * sizeof(T), hipHostMallocDefault));
@@ -177,6 +196,9 @@ struct Graph {
     bool symmetric = false;
     bool has_weights = false;
     DevBuf<int32_t> row_ptr, col, coo_src;
+    DevBuf<int2> upper;        // symmetric graphs: every undirected edge once as (u, v), u < v, CSR order
+    int64_t m_upper = 0;
+    DevBuf<int32_t> in_rp, in_col;  // directed graphs: the transpose (in-edges), built for PULL
     DevBuf<uint32_t> w;
     int32_t max_degree = 0;
     std::map<int32_t, std::unique_ptr<EdgeBlocked>> eb;  // per blocking size
@@ -189,7 +211,14 @@ struct Graph {
     int num_cus = 256;
 
     DevGraph view() const {
-        return DevGraph{n, m, row_ptr.p, col.p, has_weights ? w.p : nullptr, coo_src.p};
+        return DevGraph{n,
+                        m,
+                        row_ptr.p,
+                        col.p,
+                        has_weights ? w.p : nullptr,
+                        coo_src.p,
+                        symmetric ? row_ptr.p : in_rp.p,
+                        symmetric ? col.p : in_col.p};
     }
     std::unique_ptr<Workspace> acquire();
     void give_back(std::unique_ptr<Workspace> ws);

@@ -126,10 +126,10 @@ __global__ __launch_bounds__(kBlock) void k_pr_pull_vp(PrArgs a) {
     const double base = pr_base(a);
     double dl = 0;
     for (int v = blockIdx.x * kBlock + threadIdx.x; v < a.g.n; v += gridDim.x * kBlock) {
-        const int beg = a.g.row_ptr[v], end = a.g.row_ptr[v + 1];
+        const int beg = a.g.in_row_ptr[v], end = a.g.in_row_ptr[v + 1];
         double s = 0.0;
-        for (int e = beg; e < end; e++) s += (double)a.contrib_in[a.g.col[e]];
-        pr_apply(a, v, base, s, end - beg, dl);
+        for (int e = beg; e < end; e++) s += (double)a.contrib_in[a.g.in_col[e]];
+        pr_apply(a, v, base, s, a.g.row_ptr[v + 1] - a.g.row_ptr[v], dl);
     }
     pr_finish(a, dl);
 }
@@ -139,11 +139,11 @@ __global__ __launch_bounds__(kBlock) void k_pr_pull_wm(PrArgs a) {
     const int lane = lane_id(), wpb = kBlock / kWave;
     double dl = 0;
     for (int v = blockIdx.x * wpb + threadIdx.x / kWave; v < a.g.n; v += gridDim.x * wpb) {
-        const int beg = a.g.row_ptr[v], end = a.g.row_ptr[v + 1];
+        const int beg = a.g.in_row_ptr[v], end = a.g.in_row_ptr[v + 1];
         double s = 0.0;
-        for (int e = beg + lane; e < end; e += kWave) s += (double)a.contrib_in[a.g.col[e]];
+        for (int e = beg + lane; e < end; e += kWave) s += (double)a.contrib_in[a.g.in_col[e]];
         s = wave_sum(s);
-        if (lane == 0) pr_apply(a, v, base, s, end - beg, dl);
+        if (lane == 0) pr_apply(a, v, base, s, a.g.row_ptr[v + 1] - a.g.row_ptr[v], dl);
     }
     pr_finish(a, dl);
 }
@@ -172,12 +172,12 @@ __global__ __launch_bounds__(kBlock) void k_pr_pull_etwc(PrArgs a) {
         s_acc[tid] = 0.0;
         __syncthreads();
         const int v = vb + tid;
-        int deg = 0;
+        int deg = 0;  // out-degree (the contribution's divisor); the sums run over in-edges
         if (v < a.g.n) {
-            int beg = a.g.row_ptr[v];
-            const int end = a.g.row_ptr[v + 1];
-            deg = end - beg;
-            int size = deg;
+            int beg = a.g.in_row_ptr[v];
+            const int end = a.g.in_row_ptr[v + 1];
+            deg = a.g.row_ptr[v + 1] - a.g.row_ptr[v];
+            int size = end - beg;
             const int s2 = (size / kBlock) * kBlock;
             if (s2 > 0) {
                 const int k = atomicAdd(&q_n[2], 1);
@@ -199,14 +199,14 @@ __global__ __launch_bounds__(kBlock) void k_pr_pull_etwc(PrArgs a) {
         // stage 0: one lane per entry (sequential CSR order)
         for (int k = tid; k < q_n[0]; k += kBlock) {
             double s = 0.0;
-            for (int e = q_beg[0][k]; e < q_end[0][k]; e++) s += (double)a.contrib_in[a.g.col[e]];
+            for (int e = q_beg[0][k]; e < q_end[0][k]; e++) s += (double)a.contrib_in[a.g.in_col[e]];
             s_acc[q_slot[0][k]] += s;
         }
         __syncthreads();
         // stage 1: one wavefront per entry
         for (int k = wib; k < q_n[1]; k += kBlock / kWave) {
             double s = 0.0;
-            for (int e = q_beg[1][k] + lane; e < q_end[1][k]; e += kWave) s += (double)a.contrib_in[a.g.col[e]];
+            for (int e = q_beg[1][k] + lane; e < q_end[1][k]; e += kWave) s += (double)a.contrib_in[a.g.in_col[e]];
             s = wave_sum(s);
             if (lane == 0) s_acc[q_slot[1][k]] += s;
         }
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_pull_etwc(PrArgs a) {
         // stage 2: the whole workgroup per entry
         for (int k = 0; k < q_n[2]; k++) {
             double s = 0.0;
-            for (int e = q_beg[2][k] + tid; e < q_end[2][k]; e += kBlock) s += (double)a.contrib_in[a.g.col[e]];
+            for (int e = q_beg[2][k] + tid; e < q_end[2][k]; e += kBlock) s += (double)a.contrib_in[a.g.in_col[e]];
             s = block_sum_d(s, s_tmp);
             if (tid == 0) s_acc[q_slot[2][k]] += s;
         }
@@ -407,10 +407,10 @@ __device__ __forceinline__ int row_lower_bound(const int32_t *col, int lo, int h
 
 __global__ __launch_bounds__(kBlock) void k_seg_count(DevGraph g, int N, int S, int32_t *rp_s) {
     for (int v = blockIdx.x * kBlock + threadIdx.x; v < g.n; v += gridDim.x * kBlock) {
-        const int beg = g.row_ptr[v], end = g.row_ptr[v + 1];
+        const int beg = g.in_row_ptr[v], end = g.in_row_ptr[v + 1];
         int lo = beg;
         for (int s = 0; s < S; s++) {
-            const int hi = s == S - 1 ? end : row_lower_bound(g.col, lo, end, (long long)(s + 1) * N);
+            const int hi = s == S - 1 ? end : row_lower_bound(g.in_col, lo, end, (long long)(s + 1) * N);
             rp_s[(long long)s * (g.n + 1) + v] = hi - lo;
             lo = hi;
         }
@@ -428,12 +428,12 @@ __global__ __launch_bounds__(kBlock) void k_seg_fill(DevGraph g, int N, int s, c
         __syncthreads();
         const int v = base + tid;
         if (v < g.n) {
-            const int beg = g.row_ptr[v], end = g.row_ptr[v + 1];
-            const int lo = row_lower_bound(g.col, beg, end, (long long)s * N);
-            const int hi = row_lower_bound(g.col, lo, end, (long long)(s + 1) * N);
+            const int beg = g.in_row_ptr[v], end = g.in_row_ptr[v + 1];
+            const int lo = row_lower_bound(g.in_col, beg, end, (long long)s * N);
+            const int hi = row_lower_bound(g.in_col, lo, end, (long long)(s + 1) * N);
             if (hi - lo < kWave) {
                 int32_t *dst = col_s + rp_s[v];
-                for (int e = lo; e < hi; e++) dst[e - lo] = g.col[e];
+                for (int e = lo; e < hi; e++) dst[e - lo] = g.in_col[e];
             } else {
                 const int k = atomicAdd(&nq, 1);
                 q_lo[k] = lo;
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_fill(DevGraph g, int N, int s, c
         }
         __syncthreads();
         for (int k = wib; k < nq; k += kBlock / kWave)
-            for (int i = lane; i < q_len[k]; i += kWave) col_s[q_dst[k] + i] = g.col[q_lo[k] + i];
+            for (int i = lane; i < q_len[k]; i += kWave) col_s[q_dst[k] + i] = g.in_col[q_lo[k] + i];
         __syncthreads();
     }
 }
@@ -585,8 +585,8 @@ static PullBlocked &pull_layout(Ctx &c, Graph &G, int N) {
     pb->N = N;
     pb->S = S;
     if (S == 1) {
-        pb->rp_ptr = g.row_ptr;
-        pb->col_ptr = g.col;
+        pb->rp_ptr = g.in_row_ptr;
+        pb->col_ptr = g.in_col;
         pb->m_s = {(long long)g.m};
         pb->col_base = {0};
     } else {
@@ -649,6 +649,7 @@ double pull_layout_prepare(Graph &G, int32_t seg_vertices, hipStream_t stream) {
         std::lock_guard<std::mutex> lk(G.mu);
         if (G.pull_eb.count(S == 1 ? 0 : N)) return 0.0;
     }
+    ensure_transpose(c, G);
     hipEvent_t e0, e1;
     GG_HIP(hipEventCreate(&e0));
     GG_HIP(hipEventCreate(&e1));
@@ -683,6 +684,7 @@ void pr_run(Graph &G, const gg_schedule &sch, float damping, int iters, uint32_t
     const gg_simple_schedule &s = sch.s1;
     const bool push = s.direction == GG_PUSH;
     if (push) ensure_coo(c, G);
+    else ensure_transpose(c, G);  // directed graphs: the sums run over in-edges
     EdgeBlocked *eb = nullptr;
     if (push && s.edge_blocking) {
         edgeblock_prepare(c, G, s.blocking_size);

@@ -82,8 +82,8 @@ static void check_simple(const Graph &g, int algo, const gg_simple_schedule &s, 
     if (s.dedup_type < 0 || s.dedup_type > GG_DEDUP_BOOLMAP) throw Error(GG_ERR_INVALID_ARG, "bad dedup_type");
     if (s.delta < 1) throw Error(GG_ERR_INVALID_ARG, "delta must be >= 1");
     if (s.edge_blocking && s.blocking_size < 1) throw Error(GG_ERR_INVALID_ARG, "blocking_size must be >= 1");
-    if (s.direction == GG_PULL && !g.symmetric)
-        bad("PULL needs a symmetric graph (in-edges are read from the CSR)");
+    // PULL reads in-edges: the CSR itself on a symmetric graph, else its
+    // transpose (built once per graph on first use)
     // EdgeBlocking applies only when every edge is processed (the edge
     // processing algorithm's note): the topology-driven PageRank sweep.
     if (s.edge_blocking) {

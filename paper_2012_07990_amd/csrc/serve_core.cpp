@@ -65,7 +65,7 @@ int64_t Core::submit(int gid, int algo, int src) {
 bool Core::form_batch(Batch &b) {
     if (pending_.empty()) return false;
     Req *head = pending_.front();
-    const int lim = std::max(1, ex_->max_batch(head->algo));
+    const int lim = std::max(1, ex_->max_batch(head->gid, head->algo));
     const size_t free_bytes = budget_ > in_use_ ? budget_ - in_use_ : 0;
     std::vector<Req *> pick{head};
     for (auto it = pending_.begin() + 1; it != pending_.end() && (int)pick.size() < lim; ++it)

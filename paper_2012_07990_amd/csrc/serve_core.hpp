@@ -59,7 +59,8 @@ struct Batch {
 class Executor {
 public:
     virtual ~Executor() = default;
-    virtual int max_batch(int algo) const = 0;
+    // most queries of (graph, algorithm) one batch may hold
+    virtual int max_batch(int gid, int algo) const = 0;
     // device bytes a batch of k queries needs while it runs (results excluded)
     virtual size_t work_bytes(int gid, int algo, int k) const = 0;
     // device bytes one query's result occupies until collected

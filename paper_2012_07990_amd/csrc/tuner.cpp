@@ -29,6 +29,24 @@ static std::vector<gg_schedule> candidates(const Graph &G, int algo) {
     };
     const int lbs[] = {GG_LB_VERTEX_BASED, GG_LB_WM, GG_LB_CM, GG_LB_STRICT, GG_LB_TWC, GG_LB_ETWC, GG_LB_EDGE_ONLY};
     const float thetas[] = {0.001f, 0.01f, 0.05f, 0.2f};
+    // output-frontier creation x deduplication of a push step (configFrontierCreation,
+    // configDeduplication): FUSED with each dedup kind or none, and the two dense
+    // forms (duplicate-free by construction)
+    struct CreateDedup {
+        int create, dedup_on, dedup;
+    };
+    const CreateDedup cds[] = {{GG_CREATE_FUSED, 1, GG_DEDUP_MONOTONIC_COUNTERS},
+                               {GG_CREATE_FUSED, 1, GG_DEDUP_BITMAP},
+                               {GG_CREATE_FUSED, 1, GG_DEDUP_BOOLMAP},
+                               {GG_CREATE_FUSED, 0, GG_DEDUP_MONOTONIC_COUNTERS},
+                               {GG_CREATE_UNFUSED_BOOLMAP, 0, GG_DEDUP_MONOTONIC_COUNTERS},
+                               {GG_CREATE_UNFUSED_BITMAP, 0, GG_DEDUP_MONOTONIC_COUNTERS}};
+    auto with_cd = [](gg_simple_schedule x, const CreateDedup &cd) {
+        x.frontier_creation = cd.create;
+        x.dedup_enable = cd.dedup_on;
+        x.dedup_type = cd.dedup;
+        return x;
+    };
     gg_schedule s = default_schedule();
     switch (algo) {
     case GG_ALGO_BFS:
@@ -36,7 +54,14 @@ static std::vector<gg_schedule> candidates(const Graph &G, int algo) {
         for (int lb : lbs) {
             s = default_schedule();
             s.s1.load_balance = lb;
-            push(s);  // push only
+            // push only, under every creation x dedup choice (BC keeps its
+            // levels as queues: only the dedup choices differ there)
+            for (const CreateDedup &cd : cds) {
+                if (algo == GG_ALGO_BC && cd.create != GG_CREATE_FUSED) continue;
+                gg_schedule p = s;
+                p.s1 = with_cd(s.s1, cd);
+                push(p);
+            }
             for (float th : thetas)
                 for (int rep : {GG_REP_BITMAP, GG_REP_BOOLMAP}) {
                     gg_schedule h = s;
@@ -65,15 +90,20 @@ static std::vector<gg_schedule> candidates(const Graph &G, int algo) {
         }
         break;
     case GG_ALGO_SSSP:
+        // the near queue stays a queue: SSSP varies the deduplication only
         for (int lb : lbs)
             for (int delta : {1, 8, 64, 512, 4096})
-                for (int fused : {0, 1}) {
-                    s = default_schedule();
-                    s.s1.load_balance = lb;
-                    s.s1.delta = delta;
-                    s.s1.kernel_fusion = fused;
-                    push(s);
-                }
+                for (int fused : {0, 1})
+                    for (const CreateDedup &cd : cds) {
+                        if (cd.create != GG_CREATE_FUSED) continue;
+                        if (fused && !(cd.dedup_on && cd.dedup == GG_DEDUP_MONOTONIC_COUNTERS)) continue;
+                        s = default_schedule();
+                        s.s1 = with_cd(s.s1, cd);
+                        s.s1.load_balance = lb;
+                        s.s1.delta = delta;
+                        s.s1.kernel_fusion = fused;
+                        push(s);
+                    }
         break;
     case GG_ALGO_CC:
         for (int lb : lbs)

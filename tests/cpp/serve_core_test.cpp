@@ -26,7 +26,7 @@ struct Fake : Executor {
     int sleep_ms = 2;
     std::atomic<int> running{0}, max_running{0};
     std::atomic<int> mixed{0};
-    int max_batch(int algo) const override { return algo == 0 ? 64 : algo == 4 ? 16 : 1; }
+    int max_batch(int, int algo) const override { return algo == 0 ? 64 : algo == 4 ? 16 : 1; }
     size_t work_bytes(int, int, int k) const override { return work_per * (size_t)k; }
     size_t result_bytes(int, int) const override { return result_per; }
     void run(int, Batch &b) override {
