@@ -210,6 +210,22 @@ gg_status gg_schedule_validate(const gg_graph *g, int32_t algo, const gg_schedul
 gg_status gg_bfs(gg_graph *g, int32_t src, const gg_schedule *s, int32_t *depth_dev,
                  gg_stream_t stream, gg_stats *stats);
 /*
+ * gg_bfs for callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * BFS and outputs as gg_bfs, with its workspace carved from a fixed 40 MiB
+ * device array that each GPU holds until the process ends. It calls no
+ * hipMalloc, hipFree or allocating library routine. Limits: n <= 1,048,576
+ * (else GG_ERR_INVALID_ARG); GG_ERR_UNSUPPORTED_SCHEDULE for EDGE_ONLY
+ * (it needs the graph's COO array) and for PULL on a directed graph whose
+ * transpose has not been built yet (one PULL query through gg_bfs builds
+ * it); no stats. The graph must live on the current device. Every call on
+ * one GPU shares that GPU's array and leaves its contents behind (whatever
+ * must start at zero is cleared by each call): calls that overlap on one
+ * GPU race.
+ */
+gg_status gg_bfs_noalloc(gg_graph *g, int32_t src, const gg_schedule *s, int32_t *depth_dev,
+                         gg_stream_t stream);
+/*
  * Delta-stepping SSSP from src with the schedule's delta (priority-queue
  * schedule, configDelta): dist_dev[n] int32, INT32_MAX when unreachable.
  * Requires weights. GG_ERR_OVERFLOW when a distance would exceed INT32_MAX-1.

@@ -137,6 +137,7 @@ _sig("gg_schedule_default", [_SP])
 _sig("gg_schedule_preset", [_i32, _i32, _SP])
 _sig("gg_schedule_validate", [_P, _i32, _SP])
 _sig("gg_bfs", [_P, _i32, _SP, _P, _P, _STP])
+_sig("gg_bfs_noalloc", [_P, _i32, _SP, _P, _P])
 _sig("gg_sssp", [_P, _i32, _SP, _P, _P, _STP])
 _sig("gg_cc", [_P, _SP, _P, _P, _STP])
 _sig("gg_pagerank", [_P, _SP, ctypes.c_float, _i32, _u32, _P, _P, _STP])
@@ -265,6 +266,10 @@ def gg_bfs(graph, src, sched, depth, stream=None, stats=None):
     _check(_lib.gg_bfs(graph.handle, int(src), _sched_ptr(sched), _dptr(depth), _stream(stream),
                        _stats_ptr(stats)), "gg_bfs")
 
+
+def gg_bfs_noalloc(graph, src, sched, depth, stream=None):
+    _check(_lib.gg_bfs_noalloc(graph.handle, int(src), _sched_ptr(sched), _dptr(depth), _stream(stream)),
+           "gg_bfs_noalloc")
 
 
 def gg_sssp(graph, src, sched, dist, stream=None, stats=None):
