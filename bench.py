@@ -73,11 +73,13 @@ def parse():
     p.add_argument("--grid-deltas", default="1,8,64,512", help="delta values of the grid SSSP runs")
     p.add_argument("--grid-unfused-cap-s", type=float, default=4.0,
                    help="skip the unfused run of a grid configuration whose fused run took longer than this")
-    p.add_argument("--tune", action="store_true",
-                   help="also run the autotuner per algorithm on R-MAT 22 and report its picks beside the step's schedules")
+    p.add_argument("--no-tune", action="store_true",
+                   help="skip the autotuner section (per algorithm on R-MAT 22, its picks beside the step's schedules)")
     p.add_argument("--tune-budget-s", type=float, default=8.0, help="autotuner wall-clock budget per algorithm")
     p.add_argument("--pr-segment", type=int, default=PR_SEGMENT,
                    help="PageRank pull EdgeBlocking segment width (source vertices per segment)")
+    p.add_argument("--no-placement", action="store_true",
+                   help="skip the CPU-backend / placement section (SSSP and BFS on the 2048^2 grid and R-MAT 20)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy three times (scales rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     return p.parse_args()
@@ -122,14 +124,18 @@ def sweep_schedules(gg):
         s.threshold = th
         out["bfs"]["hybrid-etwc-%g" % th] = s
     out["bfs"]["fused-vp"] = gg.make_schedule(lb="vp", fusion=True)
-    out["bfs"]["fused-hybrid"] = gg.make_schedule(lb="vp", fusion=True, threshold=0.01,
-                                                  hybrid={"direction": gg.PULL, "pull_rep": gg.REP_BITMAP})
+    for lb in ["vp", "strict"]:
+        for th in [0.001, 0.01]:
+            out["bfs"]["fused-hybrid-%s-%g" % (lb, th)] = gg.make_schedule(
+                lb=lb, fusion=True, threshold=th, hybrid={"direction": gg.PULL, "pull_rep": gg.REP_BITMAP, "lb": "vp"})
     for d in [16, 64, 256, 1024]:
         for lb in ["wm", "etwc", "cm", "strict", "twc"]:
             out["sssp"]["%s-d%d" % (lb, d)] = gg.make_schedule(lb=lb, delta=d)
         out["sssp"]["fused-etwc-d%d" % d] = gg.make_schedule(lb="etwc", delta=d, fusion=True)
     for d in [2048, 4096, 16384, 1 << 20]:
         out["sssp"]["strict-d%d" % d] = gg.make_schedule(lb="strict", delta=d)
+        out["sssp"]["fused-strict-d%d" % d] = gg.make_schedule(lb="strict", delta=d, fusion=True)
+    out["cc"]["fused-strict"] = gg.make_schedule(lb="strict", fusion=True)
     out["sssp"]["strict-d64-nodedup"] = gg.make_schedule(lb="strict", delta=64, dedup=False)
     out["sssp"]["strict-d64-bitmapdedup"] = gg.make_schedule(lb="strict", delta=64, dedup_type=gg.DEDUP_BITMAP)
     for lb in ["vp", "wm", "etwc", "strict"]:
@@ -355,7 +361,7 @@ def main():
                 "lds_cached_sources_per_segment": PR_LDS_SOURCES,
                 "per_launch_ms_without_lds_cache": round(plain_ms, 5)}
 
-    tuned = tune_section(gg, G, scheds, run, src, edges, torch, args) if args.tune else None
+    tuned = None if args.no_tune else tune_section(gg, G, scheds, run, src, edges, torch, args)
 
     cpu, parity = None, None
     if not args.no_cpu_baseline:
@@ -367,8 +373,9 @@ def main():
     small = small_section(gg, graphgen, torch)
     grid = grid_section(gg, graphgen, torch, args.grid, [int(x) for x in args.grid_deltas.split(",")],
                         args.grid_unfused_cap_s) if args.grid else None
-    batched = None if args.no_batched else batched_section(gg, graphgen, torch)
+    batched = None if args.no_batched else batched_section(gg, graphgen, torch, args)
     serving = None if args.no_serving else serving_section(gg, graphgen, torch, args)
+    placement = None if args.no_placement else placement_section(gg, graphgen, torch)
 
     rec = {
         "metric": "GTEPS per algorithm (BFS/SSSP/CC/PR/BC); batched queries/s + p99 latency",
@@ -390,6 +397,7 @@ def main():
         "grid": grid,
         "batched": batched,
         "serving": serving,
+        "placement": placement,
     }
     print(json.dumps(rec), flush=True)
     if parity is not None and not parity["all"]:
@@ -535,19 +543,30 @@ def grid_section(gg, graphgen, torch, W, deltas, unfused_cap_s):
     return out
 
 
-def batched_section(gg, graphgen, torch):
+def batched_section(gg, graphgen, torch, args):
     """64 BFS + 16 BC sources on R-MAT 20 in one batched call each, against the
-    same sources as single-source calls (bit-identity checked on the way)."""
+    same sources as single-source calls (bit-identity checked on the way). The
+    autotuner picks the BFS and BC schedules on this graph (load balance,
+    direction and threshold); the single calls run them, and the batched
+    calls take their form from the picked direction."""
     import numpy as np
     g = graphgen.rmat(20, weights=True)
     G = gg.Graph.from_graphgen(g)
     deg = g.degrees()
     bfs_src = graphgen.sample_giant_sources(g, 64, 7)
     bc_src = bfs_src[:16]
-    sb = gg.schedule_preset(gg.ALGO_BFS, gg.PRESET_POWERLAW)
-    sb.threshold = 0.01
-    sc = gg.schedule_preset(gg.ALGO_BC, gg.PRESET_POWERLAW)
-    sc.threshold = 0.01
+    tuner = None
+    if args.no_tune:
+        sb = gg.schedule_preset(gg.ALGO_BFS, gg.PRESET_POWERLAW)
+        sb.threshold = 0.01
+        sc = gg.schedule_preset(gg.ALGO_BC, gg.PRESET_POWERLAW)
+        sc.threshold = 0.01
+    else:
+        t0 = time.perf_counter()
+        sb, _ = G.autotune(gg.ALGO_BFS, args.tune_budget_s, [int(x) for x in bfs_src[:4]])
+        sc, _ = G.autotune(gg.ALGO_BC, args.tune_budget_s, [int(x) for x in bc_src[:4]])
+        tuner = {"bfs": describe(gg, sb), "bc": describe(gg, sc), "tuner_s": round(time.perf_counter() - t0, 1)}
+        log("batched: tuned schedules %s" % tuner)
 
     def timed(f, reps=3):
         f()
@@ -560,9 +579,15 @@ def batched_section(gg, graphgen, torch):
             ts.append(time.perf_counter() - t1)
         return sorted(ts)[len(ts) // 2]
 
-    # one persistent launch per batch (fused PULL): 64 BFS sources, then the 16 BC sources
-    mb = gg.make_schedule(direction=gg.PULL, fusion=True)
-    mc = gg.make_schedule(fusion=True)
+    # one persistent launch per batch: 64 BFS sources, then the 16 BC sources,
+    # in the tuned schedules' forms with kernel fusion
+    def fused(s):
+        f = gg.make_schedule()
+        f.hybrid, f.threshold, f.s1, f.s2 = s.hybrid, s.threshold, s.s1, s.s2
+        f.s1.kernel_fusion = 1
+        return f
+    mb = fused(sb)
+    mc = fused(sc)
     d_multi = G.bfs_multi(bfs_src, mb)
     s_multi, dl_multi = G.bc_multi(bc_src, mc)
     ok = True
@@ -574,7 +599,7 @@ def batched_section(gg, graphgen, torch):
                                                                         d1.view(torch.int32)))
     t_multi = timed(lambda: (G.bfs_multi(bfs_src, mb), G.bc_multi(bc_src, mc)))
     # the same batches with one launch per level (host-driven loop)
-    mb_l, mc_l = gg.make_schedule(direction=gg.PULL), gg.make_schedule()
+    mb_l, mc_l = sb, sc
     t_levels = timed(lambda: (G.bfs_multi(bfs_src, mb_l), G.bc_multi(bc_src, mc_l)))
     t_single = timed(lambda: ([G.bfs(int(x), sb) for x in bfs_src], [G.bc(int(x), sc) for x in bc_src]), reps=1)
     reach = d_multi.cpu().numpy() >= 0
@@ -588,7 +613,8 @@ def batched_section(gg, graphgen, torch):
            "ms_batched": round(t_best * 1e3, 3), "ms_batched_persistent": round(t_multi * 1e3, 3),
            "ms_batched_launch_per_level": round(t_levels * 1e3, 3), "ms_single_calls": round(t_single * 1e3, 3),
            "speedup": round(t_single / t_best, 2), "gteps_batched": round(edges / t_best / 1e9, 2),
-           "queries_per_s": round(80 / t_best, 1), "bit_identical": ok}
+           "queries_per_s": round(80 / t_best, 1), "bit_identical": ok,
+           "schedules": {"bfs": describe(gg, sb), "bc": describe(gg, sc)}, "tuner": tuner}
     # 64 SSSP sources: on R-MAT 20 and on the 2048^2 grid, each form with its
     # fastest delta (batched 64 / single STRICT 4096 on R-MAT; 4096 for both on
     # the grid), against single calls (on the grid 4 single calls stand for the 64)
@@ -765,6 +791,36 @@ def serving_section(gg, graphgen, torch, args):
         log("serving rate %g: %s" % (rate, rec))
         out["rates"].append(rec)
     for G in Gs:
+        G.close()
+    return out
+
+
+def placement_section(gg, graphgen, torch):
+    """The CPU backend (the library's threads on the host CSR) against the GPU
+    on the same query, and the placement gg_place picks: delta-stepping SSSP
+    and BFS on the 2048^2 road-like grid and on R-MAT 20 (the paper's CPU-vs-GPU
+    comparison is delta-stepping on road graphs)."""
+    import numpy as np
+    _, nproc = host_cpu()
+    out = {"threads": nproc, "runs": []}
+    for name, make in [("grid2048", lambda: graphgen.grid(2048)), ("rmat20", lambda: graphgen.rmat(20, weights=True))]:
+        g = make()
+        G = gg.Graph.from_graphgen(g)
+        C = gg.CpuGraph.from_graphgen(g)
+        src = 0 if name.startswith("grid") else graphgen.max_degree_vertex(g)
+        grid = name.startswith("grid")
+        for algo, s in [(gg.ALGO_SSSP, gg.make_schedule(lb="cm", delta=4096, fusion=True) if grid
+                         else gg.make_schedule(lb="strict", delta=4096)),
+                        (gg.ALGO_BFS, gg.make_schedule(lb="cm", fusion=True) if grid else schedules(gg)["bfs"])]:
+            target, gpu_ms, cpu_ms = gg.place(G, C, algo, s, src, nthreads=nproc)
+            same = bool(np.array_equal(G.sssp(src, s).cpu().numpy(), C.sssp(src, 4096)) if algo == gg.ALGO_SSSP
+                        else np.array_equal(G.bfs(src, s).cpu().numpy(), C.bfs(src)))
+            rec = {"graph": name, "algo": "sssp" if algo == gg.ALGO_SSSP else "bfs", "gpu_schedule": describe(gg, s),
+                   "gpu_ms": round(gpu_ms, 3), "cpu_ms": round(cpu_ms, 3),
+                   "target": "cpu" if target == gg.TARGET_CPU else "gpu", "identical": same}
+            log("placement: %s" % rec)
+            out["runs"].append(rec)
+        C.close()
         G.close()
     return out
 

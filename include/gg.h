@@ -367,6 +367,45 @@ gg_status gg_server_stats(gg_server *srv, gg_serve_stats *out);
 /* Runs the pending queries to completion, frees uncollected results. */
 gg_status gg_server_destroy(gg_server *srv);
 
+/* ---- CPU backend and CPU-or-GPU placement ------------------------------------------------ */
+/*
+ * The same algorithms on the host with a pool of threads (the paper's
+ * Evaluation compares its CPU and GPU backends on one algorithm
+ * specification; delta-stepping on road graphs ran faster on the CPU).
+ * gg_cpu_graph_create copies a host CSR (GG_SYMMETRIC and GG_VALIDATE as for
+ * gg_graph_create_csr; GG_INPUT_DEVICE is refused). Outputs are host arrays of
+ * n entries with the GPU entry points' meanings; nthreads <= 0 uses every
+ * hardware thread. Depths, distances, labels and path counts equal the GPU's
+ * bit for bit; PageRank (fp32) and BC dependencies agree within the GPU's
+ * tolerances, and no result depends on the thread count. Errors as for the
+ * GPU entry points, with the message in gg_last_error().
+ */
+typedef struct gg_cpu_graph gg_cpu_graph;
+gg_status gg_cpu_graph_create(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col,
+                              const uint32_t *w, uint32_t flags, gg_cpu_graph **out);
+gg_status gg_cpu_graph_destroy(gg_cpu_graph *g);
+gg_status gg_cpu_bfs(gg_cpu_graph *g, int32_t src, int32_t nthreads, int32_t *depth);
+gg_status gg_cpu_sssp(gg_cpu_graph *g, int32_t src, int32_t delta, int32_t nthreads, int32_t *dist);
+gg_status gg_cpu_cc(gg_cpu_graph *g, int32_t nthreads, int32_t *label);
+gg_status gg_cpu_pagerank(gg_cpu_graph *g, float damping, int32_t iters, uint32_t flags, int32_t nthreads,
+                          float *rank);
+gg_status gg_cpu_bc(gg_cpu_graph *g, int32_t src, int32_t nthreads, uint64_t *sigma, float *delta);
+
+#define GG_TARGET_GPU 0
+#define GG_TARGET_CPU 1
+/*
+ * Place `algo` on the CPU or the GPU for this graph: the query (from src,
+ * under schedule s on the GPU, with s's delta on the CPU; PageRank 20
+ * rounds, d = 0.85) runs once to warm up and once timed on each backend, and
+ * the faster target is returned (and cached on g; gg_placement_get reads it).
+ * g and cg must hold the same graph. gpu_ms / cpu_ms (may be NULL) receive
+ * the timed runs.
+ */
+gg_status gg_place(gg_graph *g, gg_cpu_graph *cg, int32_t algo, const gg_schedule *s, int32_t src,
+                   int32_t nthreads, gg_stream_t stream, int32_t *target, double *gpu_ms, double *cpu_ms);
+/* The cached placement of `algo` (GG_ERR_NOT_FOUND before gg_place). */
+gg_status gg_placement_get(const gg_graph *g, int32_t algo, int32_t *target);
+
 #ifdef __cplusplus
 }
 #endif

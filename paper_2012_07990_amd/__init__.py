@@ -69,6 +69,7 @@ PR_NO_DANGLING = 1
 PR_NO_LDS_CACHE = 2
 STATS_COUNT_EDGES = 1
 STATS_TIME_KERNELS = 2
+TARGET_GPU, TARGET_CPU = 0, 1
 INT32_MAX = 2**31 - 1
 
 
@@ -180,6 +181,16 @@ _sig("gg_server_poll", [_P, _i64, _P, _u32, _RP])
 _sig("gg_server_wait", [_P, _i64, ctypes.c_double, _P, _u32, _RP])
 _sig("gg_server_stats", [_P, ctypes.POINTER(ServeStats)])
 _sig("gg_server_destroy", [_P])
+_sig("gg_cpu_graph_create", [_i32, ctypes.c_int64, _P, _P, _P, _u32, ctypes.POINTER(ctypes.c_void_p)])
+_sig("gg_cpu_graph_destroy", [_P])
+_sig("gg_cpu_bfs", [_P, _i32, _i32, _P])
+_sig("gg_cpu_sssp", [_P, _i32, _i32, _i32, _P])
+_sig("gg_cpu_cc", [_P, _i32, _P])
+_sig("gg_cpu_pagerank", [_P, ctypes.c_float, _i32, _u32, _i32, _P])
+_sig("gg_cpu_bc", [_P, _i32, _i32, _P, _P])
+_sig("gg_place", [_P, _P, _i32, _SP, _i32, _i32, _P, ctypes.POINTER(ctypes.c_int32),
+                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)])
+_sig("gg_placement_get", [_P, _i32, ctypes.POINTER(ctypes.c_int32)])
 
 
 class GGError(RuntimeError):
@@ -560,6 +571,76 @@ def load_tuned(path: str, checksum: str) -> dict:
     ids = {v: k for k, v in ALGO_NAMES.items()}
     entry = _read_store(path).get(checksum, {})
     return {ids[name]: (schedule_from_dict(e["schedule"]), float(e["ms"])) for name, e in entry.items()}
+
+
+class CpuGraph:
+    """Host copy of a CSR graph for the CPU backend (the library's threads;
+    numpy in, numpy out)."""
+
+    def __init__(self, n, row_ptr, col, w=None, symmetric=True, validate=False):
+        rp = np.ascontiguousarray(np.asarray(row_ptr, dtype=np.int32))
+        c = np.ascontiguousarray(np.asarray(col, dtype=np.int32))
+        ww = np.ascontiguousarray(np.asarray(w, dtype=np.uint32)) if w is not None else None
+        flags = (SYMMETRIC if symmetric else 0) | (VALIDATE if validate else 0)
+        h = ctypes.c_void_p()
+        _check(_lib.gg_cpu_graph_create(int(n), int(c.size), ctypes.c_void_p(rp.ctypes.data),
+                                        ctypes.c_void_p(c.ctypes.data) if c.size else None,
+                                        ctypes.c_void_p(ww.ctypes.data) if ww is not None and ww.size else None,
+                                        flags, ctypes.byref(h)), "gg_cpu_graph_create")
+        self.handle, self.n, self.m, self.symmetric = h, int(n), int(c.size), symmetric
+
+    @classmethod
+    def from_graphgen(cls, g, **kw) -> "CpuGraph":
+        return cls(g.n, g.row_ptr, g.col, g.w, **kw)
+
+    def bfs(self, src, nthreads=0):
+        out = np.empty(self.n, dtype=np.int32)
+        _check(_lib.gg_cpu_bfs(self.handle, int(src), int(nthreads), ctypes.c_void_p(out.ctypes.data)),
+               "gg_cpu_bfs")
+        return out
+
+    def sssp(self, src, delta=64, nthreads=0):
+        out = np.empty(self.n, dtype=np.int32)
+        _check(_lib.gg_cpu_sssp(self.handle, int(src), int(delta), int(nthreads), ctypes.c_void_p(out.ctypes.data)),
+               "gg_cpu_sssp")
+        return out
+
+    def cc(self, nthreads=0):
+        out = np.empty(self.n, dtype=np.int32)
+        _check(_lib.gg_cpu_cc(self.handle, int(nthreads), ctypes.c_void_p(out.ctypes.data)), "gg_cpu_cc")
+        return out
+
+    def pagerank(self, damping=0.85, iters=20, dangling=True, nthreads=0):
+        out = np.empty(self.n, dtype=np.float32)
+        _check(_lib.gg_cpu_pagerank(self.handle, float(damping), int(iters), 0 if dangling else PR_NO_DANGLING,
+                                    int(nthreads), ctypes.c_void_p(out.ctypes.data)), "gg_cpu_pagerank")
+        return out
+
+    def bc(self, src, nthreads=0):
+        sigma = np.empty(self.n, dtype=np.uint64)
+        delta = np.empty(self.n, dtype=np.float32)
+        _check(_lib.gg_cpu_bc(self.handle, int(src), int(nthreads), ctypes.c_void_p(sigma.ctypes.data),
+                              ctypes.c_void_p(delta.ctypes.data)), "gg_cpu_bc")
+        return sigma, delta
+
+    def close(self):
+        if self.handle:
+            _lib.gg_cpu_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def place(graph, cpu_graph, algo, sched=None, src=0, nthreads=0, stream=None):
+    """gg_place: time `algo` on both backends; returns (target, gpu_ms, cpu_ms)."""
+    t, g_ms, c_ms = ctypes.c_int32(), ctypes.c_double(), ctypes.c_double()
+    _check(_lib.gg_place(graph.handle, cpu_graph.handle, int(algo), _sched_ptr(sched), int(src), int(nthreads),
+                         _stream(stream), ctypes.byref(t), ctypes.byref(g_ms), ctypes.byref(c_ms)), "gg_place")
+    return t.value, g_ms.value, c_ms.value
 
 
 class Server:

@@ -101,6 +101,7 @@ struct FusedBfsArgs {
     float threshold;
     GridBarrier bar;
     unsigned long long *ecount;
+    long long *scan, *scan_part;  // STRICT: the frontier's degree scan and per-workgroup sums
 };
 
 // S2: 0 = no pull schedule, 1 = pull over a boolmap, 2 = pull over a bitmap
@@ -129,7 +130,10 @@ __global__ __launch_bounds__(kBlock) void k_bfs_fused(FusedBfsArgs a) {
             if constexpr (LB == GG_LB_VERTEX_BASED) lb_vp<kCreateFused, kDedupNone, false>(a.g, src, f, o, t, ne);
             else if constexpr (LB == GG_LB_WM) lb_wm<kCreateFused, kDedupNone>(a.g, src, f, o, t, ne);
             else if constexpr (LB == GG_LB_CM) lb_cm<kCreateFused, kDedupNone, false>(a.g, src, f, o, t, ne);
-            else lb_etwc<kCreateFused, kDedupNone, false>(a.g, src, f, o, t, ne);
+            else if constexpr (LB == GG_LB_STRICT) {
+                if (!grid_degree_scan(a.g, src, a.scan, a.scan_part, bar)) break;
+                lb_strict<kCreateFused, kDedupNone>(a.g, src, a.scan, f, o, t, ne);
+            } else lb_etwc<kCreateFused, kDedupNone, false>(a.g, src, f, o, t, ne);
         } else {
             pulls++;
             // dense input map from the queue: clear, barrier, scatter, barrier
@@ -179,7 +183,8 @@ void bfs_fused(Ctx &c, Graph &G, Workspace &ws, int32_t src, const gg_schedule &
     case GG_LB_WM: kern = fused_kernel_s2<GG_LB_WM>(s2); break;
     case GG_LB_CM: kern = fused_kernel_s2<GG_LB_CM>(s2); break;
     case GG_LB_ETWC: kern = fused_kernel_s2<GG_LB_ETWC>(s2); break;
-    default: throw Error(GG_ERR_UNSUPPORTED_SCHEDULE, "kernel fusion supports VERTEX_BASED, WM, CM and ETWC");
+    case GG_LB_STRICT: kern = fused_kernel_s2<GG_LB_STRICT>(s2); break;
+    default: throw Error(GG_ERR_UNSUPPORTED_SCHEDULE, "kernel fusion supports VERTEX_BASED, WM, CM, ETWC and STRICT");
     }
     const size_t nb = ((size_t)g.n + 255) / 256 * 256;
     ws.q[0].ensure((size_t)g.n);
@@ -195,8 +200,12 @@ void bfs_fused(Ctx &c, Graph &G, Workspace &ws, int32_t src, const gg_schedule &
     fill_i32(c, ws.counters.p, 1, 1);  // |F0| = 1
     c.launches++;
     const int blocks = fused_grid_for(kern, G, c.num_cus);
+    if (s1.load_balance == GG_LB_STRICT) {
+        ws.scan.ensure((size_t)g.n + 1);
+        ws.scan_part.ensure((size_t)blocks);
+    }
     FusedBfsArgs a{g, depth, ws.q[0].p, ws.q[1].p, ws.counters.p, ws.boolmap[0].p, ws.bitmap[0].p,
-                   s.threshold, prepare_barrier(c, ws, blocks), c.edge_counter};
+                   s.threshold, prepare_barrier(c, ws, blocks), c.edge_counter, ws.scan.p, ws.scan_part.p};
     void *args[] = {&a};
     launch_cooperative(c, kern, blocks, args);
     check_barrier(c, ws);

@@ -167,6 +167,7 @@ struct FusedCcArgs {
     int32_t *ctr;  // [0..2] changed flags (rotating), [3] rounds
     GridBarrier bar;
     unsigned long long *ecount;
+    long long *scan, *scan_part;  // STRICT: the degree scan of every vertex (computed once)
 };
 
 template <int LB>
@@ -177,7 +178,9 @@ __global__ __launch_bounds__(kBlock) void k_cc_fused(FusedCcArgs a) {
     const SrcQueue src{a.ids, a.g.n};
     OutFrontier o{};  // hooks emit nothing
     int r = 0;
-    for (;;) {
+    bool ok = true;
+    if constexpr (LB == GG_LB_STRICT) ok = grid_degree_scan(a.g, src, a.scan, a.scan_part, bar);
+    for (; ok;) {
         // round r hooks into flag r%3 and everyone reads it after the second
         // barrier; flag (r+1)%3 was last read before round r-1's barriers
         int32_t *changed = a.ctr + (r % 3);
@@ -187,6 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_cc_fused(FusedCcArgs a) {
         if constexpr (LB == GG_LB_VERTEX_BASED) lb_vp<kCreateBoolmap, kDedupNone, false>(a.g, src, f, o, t, ne);
         else if constexpr (LB == GG_LB_WM) lb_wm<kCreateBoolmap, kDedupNone>(a.g, src, f, o, t, ne);
         else if constexpr (LB == GG_LB_CM) lb_cm<kCreateBoolmap, kDedupNone, false>(a.g, src, f, o, t, ne);
+        else if constexpr (LB == GG_LB_STRICT) lb_strict<kCreateBoolmap, kDedupNone>(a.g, src, a.scan, f, o, t, ne);
         else lb_etwc<kCreateBoolmap, kDedupNone, false>(a.g, src, f, o, t, ne);
         if (!grid_sync(bar)) break;
         cc_compress_dev(a.label, a.g.n, t);
@@ -223,10 +227,17 @@ void cc_run(Graph &G, const gg_schedule &sch, int32_t *label, hipStream_t stream
         case GG_LB_WM: kern = (const void *)k_cc_fused<GG_LB_WM>; break;
         case GG_LB_CM: kern = (const void *)k_cc_fused<GG_LB_CM>; break;
         case GG_LB_ETWC: kern = (const void *)k_cc_fused<GG_LB_ETWC>; break;
-        default: throw Error(GG_ERR_UNSUPPORTED_SCHEDULE, "kernel fusion supports VERTEX_BASED, WM, CM and ETWC");
+        case GG_LB_STRICT: kern = (const void *)k_cc_fused<GG_LB_STRICT>; break;
+        default:
+            throw Error(GG_ERR_UNSUPPORTED_SCHEDULE, "kernel fusion supports VERTEX_BASED, WM, CM, ETWC and STRICT");
         }
         const int blocks = fused_grid_for(kern, G, c.num_cus);
-        FusedCcArgs a{g, label, ws->aux_i32[0].p, ws->counters.p, prepare_barrier(c, *ws, blocks), c.edge_counter};
+        if (s.load_balance == GG_LB_STRICT) {
+            ws->scan.ensure((size_t)n + 1);
+            ws->scan_part.ensure((size_t)blocks);
+        }
+        FusedCcArgs a{g,          label, ws->aux_i32[0].p, ws->counters.p, prepare_barrier(c, *ws, blocks),
+                      c.edge_counter, ws->scan.p, ws->scan_part.p};
         void *args[] = {&a};
         launch_cooperative(c, kern, blocks, args);
         check_barrier(c, *ws);

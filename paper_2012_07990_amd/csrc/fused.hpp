@@ -12,6 +12,7 @@
 // that every workgroup checks, so all waves leave the kernel.
 #pragma once
 
+#include "frontier.hpp"
 #include "ops.hpp"
 
 namespace gg {
@@ -79,6 +80,85 @@ __device__ __forceinline__ bool grid_sync(GridBarrier &b) {
     }
     __syncthreads();
     return s_abort == 0;
+}
+
+// STRICT inside a persistent kernel: the exclusive scan of the frontier's
+// degrees, scan[0..size] (scan[size] = total), computed by the whole grid.
+// Each workgroup sums the degrees of its contiguous slice into part[block];
+// after a grid barrier every workgroup adds up the slices before its own and
+// writes its slice's prefix sums, 256 at a time; a second barrier publishes
+// the scan. Returns false when a barrier was aborted.
+template <class Src>
+__device__ bool grid_degree_scan(const DevGraph &g, const Src &src, long long *scan, long long *part,
+                                 GridBarrier &bar) {
+    __shared__ long long s_red[kBlock / kWave];
+    __shared__ long long s_off;
+    const int size = src.size;
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x, tid = (int)threadIdx.x;
+    const int slice = (size + nb - 1) / nb;
+    const int lo = min(size, b * slice), hi = min(size, lo + slice);
+    long long sum = 0;
+    for (int i = lo + tid; i < hi; i += kBlock) {
+        const int u = src.get(i);
+        sum += g.row_ptr[u + 1] - g.row_ptr[u];
+    }
+    sum = wave_sum(sum);
+    if (lane_id() == 0) s_red[tid / kWave] = sum;
+    __syncthreads();
+    if (tid == 0) {
+        long long t = 0;
+        for (int w = 0; w < kBlock / kWave; w++) t += s_red[w];
+        part[b] = t;
+    }
+    if (!grid_sync(bar)) return false;
+    // the slices before this one (and, for the last workgroup, all of them)
+    long long before = 0, all = 0;
+    for (int j = tid; j < nb; j += kBlock) {
+        const long long v = part[j];
+        if (j < b) before += v;
+        all += v;
+    }
+    before = wave_sum(before);
+    all = wave_sum(all);
+    __syncthreads();
+    if (lane_id() == 0) s_red[tid / kWave] = before;
+    __syncthreads();
+    if (tid == 0) {
+        long long t = 0;
+        for (int w = 0; w < kBlock / kWave; w++) t += s_red[w];
+        s_off = t;
+    }
+    __syncthreads();
+    if (lane_id() == 0) s_red[tid / kWave] = all;
+    __syncthreads();
+    if (b == nb - 1 && tid == 0) {
+        long long t = 0;
+        for (int w = 0; w < kBlock / kWave; w++) t += s_red[w];
+        scan[size] = t;
+    }
+    long long off = s_off;
+    for (int base = lo; base < hi; base += kBlock) {
+        const int i = base + tid;
+        long long d = 0;
+        if (i < hi) {
+            const int u = src.get(i);
+            d = g.row_ptr[u + 1] - g.row_ptr[u];
+        }
+        const long long incl = wave_incl_scan64(d);
+        __syncthreads();
+        if (lane_id() == kWave - 1) s_red[tid / kWave] = incl;
+        __syncthreads();
+        long long wbefore = 0, tile = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / kWave; w++) {
+            const long long v = s_red[w];
+            if (w < tid / kWave) wbefore += v;
+            tile += v;
+        }
+        if (i < hi) scan[i] = off + wbefore + incl - d;
+        off += tile;
+    }
+    return grid_sync(bar);
 }
 
 // Co-resident grid for a persistent kernel: `per_cu` workgroups (of

@@ -204,6 +204,7 @@ struct Graph {
     std::map<int32_t, std::unique_ptr<EdgeBlocked>> eb;  // per blocking size
     std::map<int32_t, std::unique_ptr<PullBlocked>> pull_eb;  // STRICT pull partitions per segment width
     std::map<int, std::pair<gg_schedule, double>> tuned;       // autotuner winners (schedule, ms) per algorithm
+    std::map<int, int> placement;                              // measured CPU-or-GPU target per algorithm
     std::mutex mu;
     std::vector<std::unique_ptr<Workspace>> pool;
     size_t leased = 0;  // lease_bytes of the workspaces leased out now

@@ -275,21 +275,41 @@ __global__ __launch_bounds__(kWave *kPrWaves) __attribute__((amdgpu_waves_per_eu
         __syncthreads();
     }
     float *cv = vals[wib];
-    for (long long c = (long long)blockIdx.x * kPrWaves + wib; c < nchunks; c += (long long)gridDim.x * kPrWaves) {
+    // Column loads, then gathers, without branches in between (a conditional
+    // per edge made the compiler wait for each load in turn); edges past a
+    // chunk's end re-read its last edge and are not stored. The column stream
+    // is read once: non-temporal loads keep it from evicting the segment's
+    // contributions from L2. The loop is software-pipelined: the next
+    // chunk's columns are requested as soon as this chunk's gathers are, so
+    // they arrive during this chunk's reduction.
+    constexpr int kPer = kPrChunk / kWave;
+    const long long cstride = (long long)gridDim.x * kPrWaves;
+    long long c = (long long)blockIdx.x * kPrWaves + wib;
+    int cnext[kPer];
+    auto load_cols = [&](long long cc) {
+        const long long F0 = cc * kPrChunk, F1 = (F0 + kPrChunk < m) ? F0 + kPrChunk : m;
+#pragma unroll
+        for (int k = 0; k < kPer; k++) {
+            const long long e = F0 + k * kWave + lane;
+            cnext[k] = __builtin_nontemporal_load(&col[e < F1 ? e : F1 - 1]);
+        }
+    };
+    if (c < nchunks) load_cols(c);
+    for (; c < nchunks; c += cstride) {
         const long long E0 = c * kPrChunk, E1 = (E0 + kPrChunk < m) ? E0 + kPrChunk : m;
-        // all column loads, then all gathers, without branches in between (a
-        // conditional per edge made the compiler wait for each load in turn);
-        // edges past the chunk's end re-read its last edge and are not stored.
-        // The column stream is read once: non-temporal loads keep it from
-        // evicting the segment's contributions from L2
-        constexpr int kPer = kPrChunk / kWave;
+        const int r0 = chunk_rows[2 * c], r1 = chunk_rows[2 * c + 1];
         int cidx[kPer];
         float cval[kPer];
 #pragma unroll
-        for (int k = 0; k < kPer; k++) {
-            const long long e = E0 + k * kWave + lane;
-            cidx[k] = __builtin_nontemporal_load(&col[e < E1 ? e : E1 - 1]);
-        }
+        for (int k = 0; k < kPer; k++) cidx[k] = cnext[k];
+        // the offsets of the chunk's first 128 rows travel with its gathers
+        // (a row past r1 re-reads r1's): vector loads complete in order, so a
+        // row offset requested after the next chunk's columns would make the
+        // reduction wait for those too
+        const int rf = r0 + lane <= r1 ? r0 + lane : r1;
+        const int rs = r0 + kWave + lane <= r1 ? r0 + kWave + lane : r1;
+        const int rb_first = rp[rf], re_first = rp[rf + 1];
+        const int rb_second = rp[rs], re_second = rp[rs + 1];
         if constexpr (HK > 0) {
             // a cached source's lane reads contrib[0] (one shared line for the
             // wavefront) and takes the LDS value; the rest read LDS entry 0
@@ -306,29 +326,44 @@ __global__ __launch_bounds__(kWave *kPrWaves) __attribute__((amdgpu_waves_per_eu
 #pragma unroll
             for (int k = 0; k < kPer; k++) cval[k] = contrib[cidx[k]];
         }
+        if (c + cstride < nchunks) load_cols(c + cstride);
 #pragma unroll
         for (int k = 0; k < kPer; k++) {
             const long long e = E0 + k * kWave + lane;
             if (e < E1) cv[e - E0] = cval[k];
         }
-        const int r0 = chunk_rows[2 * c], r1 = chunk_rows[2 * c + 1];
         wave_lds_sync();
         // short rows (< 32 in-chunk edges): one lane each, in CSR order; long
-        // rows: the whole wavefront, lane-strided sums reduced by a butterfly
+        // rows: the whole wavefront, lane-strided sums reduced by a butterfly.
+        // A row inside the chunk adds its sum to accum with an atomic whose
+        // result is not awaited: within one launch (one source segment) no
+        // other add reaches that row, so the value equals a read-modify-write
+        // in launch order, without the wait for the read
         for (int rbase = r0; rbase <= r1; rbase += kWave) {
             const int r = rbase + lane;
             int lo = 0, hi = 0, whole = 0;
             if (r <= r1) {
-                const long long rb = rp[r], re = rp[r + 1];
+                const long long rb = rbase == r0 ? rb_first : rbase == r0 + kWave ? rb_second : rp[r];
+                const long long re = rbase == r0 ? re_first : rbase == r0 + kWave ? re_second : rp[r + 1];
                 lo = (int)((rb > E0 ? rb : E0) - E0);
                 hi = (int)((re < E1 ? re : E1) - E0);
                 whole = rb >= E0 && re <= E1;
             }
             const bool lng = hi - lo >= 32;
             if (r <= r1 && !lng) {
+                // four LDS reads in flight per step, added in row order (the
+                // additions, and so the rounding, are the plain loop's)
                 double sum = 0.0;
-                for (int i = lo; i < hi; i++) sum += (double)cv[i];
-                if (whole && hi > lo) accum[r] += sum;
+                int i = lo;
+                for (; i + 4 <= hi; i += 4) {
+                    const float x0 = cv[i], x1 = cv[i + 1], x2 = cv[i + 2], x3 = cv[i + 3];
+                    sum += (double)x0;
+                    sum += (double)x1;
+                    sum += (double)x2;
+                    sum += (double)x3;
+                }
+                for (; i < hi; i++) sum += (double)cv[i];
+                if (whole && hi > lo) (void)atomic_add_f64(&accum[r], sum);
                 if (r == r0) head[c] = sum;
                 if (r == r1) tail[c] = sum;
             }
@@ -342,7 +377,7 @@ __global__ __launch_bounds__(kWave *kPrWaves) __attribute__((amdgpu_waves_per_eu
                 for (int i = llo + lane; i < lhi; i += kWave) sum += (double)cv[i];
                 sum = wave_sum(sum);
                 if (lane == 0) {
-                    if (wh) accum[rr] += sum;
+                    if (wh) (void)atomic_add_f64(&accum[rr], sum);
                     if (rr == r0) head[c] = sum;
                     if (rr == r1) tail[c] = sum;
                 }

@@ -120,8 +120,9 @@ static void check_simple(const Graph &g, int algo, const gg_simple_schedule &s, 
         if (algo != GG_ALGO_BFS && algo != GG_ALGO_SSSP && algo != GG_ALGO_CC)
             bad("kernel fusion is available for BFS, SSSP and CC loops");
         if (s.load_balance != GG_LB_VERTEX_BASED && s.load_balance != GG_LB_WM && s.load_balance != GG_LB_CM &&
-            s.load_balance != GG_LB_ETWC)
-            bad("kernel fusion supports VERTEX_BASED, WM, CM and ETWC (device-side load balancers)");
+            s.load_balance != GG_LB_ETWC && s.load_balance != GG_LB_STRICT)
+            bad("kernel fusion supports VERTEX_BASED, WM, CM, ETWC and STRICT (device-side load balancers; "
+                "STRICT's degree scan runs inside the persistent grid)");
         if (s.frontier_creation != GG_CREATE_FUSED) bad("kernel fusion keeps the frontier as a queue (FUSED creation)");
         if (algo != GG_ALGO_BFS && s.direction == GG_PULL) bad("fused loops run PUSH");
     }

@@ -21,6 +21,8 @@
 
 namespace gg {
 
+static_assert(serve::kAdmissionStatus == GG_ERR_ADMISSION, "admission status mismatch");
+
 struct GpuExecutor : serve::Executor {
     static constexpr int kMaxGraphs = 64;
     Graph *graphs[kMaxGraphs] = {};
@@ -190,9 +192,20 @@ struct GpuExecutor : serve::Executor {
         r.result = nullptr;
     }
 
-    size_t idle_bytes() override {
+    // derived layouts a graph already had when it was added belong to the
+    // caller's graph (like its CSR); those built since are charged
+    size_t layout_base[kMaxGraphs] = {};
+    size_t pinned_bytes() override {
         size_t b = 0;
-        for (int i = 0; i < ngraphs; i++) b += graphs[i]->pooled_bytes() + graphs[i]->layout_bytes();
+        for (int i = 0; i < ngraphs; i++) {
+            const size_t l = graphs[i]->layout_bytes();
+            b += l > layout_base[i] ? l - layout_base[i] : 0;
+        }
+        return b;
+    }
+    size_t idle_bytes() override {
+        size_t b = pinned_bytes();
+        for (int i = 0; i < ngraphs; i++) b += graphs[i]->pooled_bytes();
         return b;
     }
 
@@ -283,6 +296,7 @@ gg_status gg_server_add_graph(gg_server *srv, gg_graph *g, int32_t *gid) {
         require(srv->ex->ngraphs < GpuExecutor::kMaxGraphs, GG_ERR_INVALID_ARG, "too many graphs");
         require(g->g.symmetric, GG_ERR_INVALID_ARG, "served graphs must be symmetric (GG_SYMMETRIC)");
         srv->ex->graphs[srv->ex->ngraphs] = &g->g;
+        srv->ex->layout_base[srv->ex->ngraphs] = g->g.layout_bytes();
         *gid = srv->ex->ngraphs++;
     });
 }

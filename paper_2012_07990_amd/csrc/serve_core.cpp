@@ -40,10 +40,11 @@ void Core::shutdown() {
 int64_t Core::submit(int gid, int algo, int src) {
     const size_t one = ex_->work_bytes(gid, algo, 1) + ex_->result_bytes(gid, algo);
     std::lock_guard<std::mutex> lk(mu_);
-    if (one > budget_) {
+    const size_t pinned = ex_->pinned_bytes();
+    if (one > budget_ || pinned > budget_ - one) {
         st_.rejected++;
-        throw AdmissionError("query footprint " + std::to_string(one) + " B exceeds the serving budget " +
-                             std::to_string(budget_) + " B");
+        throw AdmissionError("query footprint " + std::to_string(one) + " B plus " + std::to_string(pinned) +
+                             " B of derived layouts exceeds the serving budget " + std::to_string(budget_) + " B");
     }
     auto r = std::make_unique<Req>();
     r->ticket = next_ticket_++;
@@ -63,7 +64,23 @@ int64_t Core::submit(int gid, int algo, int src) {
 // Oldest pending query first; then every pending query of the same graph and
 // algorithm, up to the batch limit and the memory that is free now.
 bool Core::form_batch(Batch &b) {
-    if (pending_.empty()) return false;
+    while (!pending_.empty()) {
+        if (try_batch(b)) return true;
+        if (running_ != 0 || in_use_ != 0) return false;  // wait for memory
+        // nothing can free memory any more: the head query can never run
+        Req *head = pending_.front();
+        pending_.pop_front();
+        head->status = kAdmissionStatus;
+        head->result_bytes = 0;
+        head->t_start = head->t_done = Clock::now();
+        head->done = true;
+        st_.rejected++;
+        cv_done_.notify_all();
+    }
+    return false;
+}
+
+bool Core::try_batch(Batch &b) {
     Req *head = pending_.front();
     const int lim = std::max(1, ex_->max_batch(head->gid, head->algo));
     const size_t free_bytes = budget_ > in_use_ ? budget_ - in_use_ : 0;
@@ -86,13 +103,14 @@ bool Core::form_batch(Batch &b) {
             b.reqs = pick;
             b.work_bytes = ex_->work_bytes(head->gid, head->algo, (int)pick.size());
             in_use_ += need;
+            running_++;
             st_.bytes_peak = std::max(st_.bytes_peak, in_use_ + idle);
             for (Req *r : pick) pending_.erase(std::find(pending_.begin(), pending_.end(), r));
             return true;
         }
         pick.pop_back();
     }
-    return false;  // not even one query fits: wait for memory
+    return false;  // not even one query fits
 }
 
 void Core::worker(int id) {
@@ -114,6 +132,7 @@ void Core::worker(int id) {
         {
             std::lock_guard<std::mutex> lk(mu_);
             in_use_ -= b.work_bytes;
+            running_--;
             for (Req *r : b.reqs) {
                 r->t_done = t1;
                 r->done = true;

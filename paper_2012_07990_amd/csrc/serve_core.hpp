@@ -14,6 +14,9 @@
 // streams. A result stays charged to the budget until the client collects
 // it. Invariant: device bytes held <= in_use + idle <= budget, given that
 // work_bytes() bounds what a batch allocates beyond idle memory it reuses.
+// A query that cannot fit even alone while nothing runs and nothing is
+// charged (idle memory that trim() cannot free fills the budget) fails with
+// an admission status instead of waiting forever.
 #pragma once
 
 #include <chrono>
@@ -33,6 +36,9 @@ namespace gg {
 namespace serve {
 
 using Clock = std::chrono::steady_clock;
+
+// status of a query refused because it can never fit (the C ABI's GG_ERR_ADMISSION)
+constexpr int kAdmissionStatus = 6;
 
 // thrown by submit() when a single query can never fit the memory budget
 struct AdmissionError : std::runtime_error {
@@ -75,6 +81,8 @@ public:
     virtual size_t idle_bytes() { return 0; }
     // free idle bytes (best effort) until idle_bytes() <= target
     virtual void trim(size_t target) { (void)target; }
+    // the part of idle_bytes() that trim() cannot free (derived layouts)
+    virtual size_t pinned_bytes() { return 0; }
 };
 
 struct Stats {
@@ -105,6 +113,7 @@ public:
 private:
     void worker(int id);
     bool form_batch(Batch &b);  // called with mu held
+    bool try_batch(Batch &b);   // the head query's batch, if it fits now (mu held)
 
     Executor *ex_;
     size_t budget_;
@@ -115,6 +124,7 @@ private:
     std::vector<std::thread> threads_;
     int64_t next_ticket_ = 1;
     size_t in_use_ = 0;
+    int running_ = 0;  // batches on the device now
     bool stop_ = false;
     Stats st_;
 };

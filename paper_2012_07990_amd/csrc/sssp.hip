@@ -180,6 +180,7 @@ struct FusedSsspArgs {
     int32_t delta;
     GridBarrier bar;
     unsigned long long *ecount;
+    long long *scan, *scan_part;  // STRICT: the near queue's degree scan and per-workgroup sums
 };
 
 template <int LB>
@@ -209,7 +210,10 @@ __global__ __launch_bounds__(kBlock) void k_sssp_fused(FusedSsspArgs a) {
             if constexpr (LB == GG_LB_VERTEX_BASED) lb_vp<kCreateFused, kDedupMonotonic, false>(a.g, src, f, o, t, ne);
             else if constexpr (LB == GG_LB_WM) lb_wm<kCreateFused, kDedupMonotonic>(a.g, src, f, o, t, ne);
             else if constexpr (LB == GG_LB_CM) lb_cm<kCreateFused, kDedupMonotonic, false>(a.g, src, f, o, t, ne);
-            else lb_etwc<kCreateFused, kDedupMonotonic, false>(a.g, src, f, o, t, ne);
+            else if constexpr (LB == GG_LB_STRICT) {
+                if (!grid_degree_scan(a.g, src, a.scan, a.scan_part, bar)) break;
+                lb_strict<kCreateFused, kDedupMonotonic>(a.g, src, a.scan, f, o, t, ne);
+            } else lb_etwc<kCreateFused, kDedupMonotonic, false>(a.g, src, f, o, t, ne);
             rounds++;
         } else {
             const int fc = load_relaxed(farc);
@@ -247,7 +251,8 @@ static void sssp_fused(Ctx &c, Graph &G, Workspace &ws, int32_t src, const gg_si
     case GG_LB_WM: kern = (const void *)k_sssp_fused<GG_LB_WM>; break;
     case GG_LB_CM: kern = (const void *)k_sssp_fused<GG_LB_CM>; break;
     case GG_LB_ETWC: kern = (const void *)k_sssp_fused<GG_LB_ETWC>; break;
-    default: throw Error(GG_ERR_UNSUPPORTED_SCHEDULE, "kernel fusion supports VERTEX_BASED, WM, CM and ETWC");
+    case GG_LB_STRICT: kern = (const void *)k_sssp_fused<GG_LB_STRICT>; break;
+    default: throw Error(GG_ERR_UNSUPPORTED_SCHEDULE, "kernel fusion supports VERTEX_BASED, WM, CM, ETWC and STRICT");
     }
     const int n = g.n;
     ws.q[0].ensure(n);
@@ -267,8 +272,13 @@ static void sssp_fused(Ctx &c, Graph &G, Workspace &ws, int32_t src, const gg_si
     c.launches++;
     fill_i32(c, ws.counters.p, 1, 1);
     const int blocks = fused_grid_for(kern, G, c.num_cus);
+    if (s.load_balance == GG_LB_STRICT) {
+        ws.scan.ensure((size_t)n + 1);
+        ws.scan_part.ensure((size_t)blocks);
+    }
     FusedSsspArgs a{g, dist, ws.q[0].p, ws.q[1].p, ws.aux_i32[0].p, ws.aux_i32[1].p, ws.counters.p, ws.tags.p,
-                    ws.aux_i32[2].p, n, s.delta, prepare_barrier(c, ws, blocks), c.edge_counter};
+                    ws.aux_i32[2].p, n, s.delta, prepare_barrier(c, ws, blocks), c.edge_counter, ws.scan.p,
+                    ws.scan_part.p};
     void *args[] = {&a};
     launch_cooperative(c, kern, blocks, args);
     check_barrier(c, ws);

@@ -90,9 +90,12 @@ static std::vector<gg_schedule> candidates(const Graph &G, int algo) {
         }
         break;
     case GG_ALGO_SSSP:
-        // the near queue stays a queue: SSSP varies the deduplication only
-        for (int lb : lbs)
-            for (int delta : {1, 8, 64, 512, 4096})
+        // the near queue stays a queue: SSSP varies the deduplication only.
+        // Wide buckets first: the first halving round times every candidate
+        // once in this order, and a budget that runs out there keeps the
+        // narrow-bucket ones (the slowest on every graph measured) untimed
+        for (int delta : {4096, 512, 64, 8, 1})
+            for (int lb : lbs)
                 for (int fused : {0, 1})
                     for (const CreateDedup &cd : cds) {
                         if (cd.create != GG_CREATE_FUSED) continue;

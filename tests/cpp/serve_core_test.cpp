@@ -210,6 +210,48 @@ static void test_idle_bytes_charged_and_trimmed() {
     std::puts("ok idle bytes");
 }
 
+// Idle memory that cannot be trimmed (derived layouts) larger than what a
+// query needs: the query fails with the admission status instead of waiting
+// forever, at submission when the pinned bytes are known, else when nothing
+// runs and nothing is charged.
+struct Pinned : Fake {
+    std::atomic<size_t> pinned{0};
+    size_t idle_bytes() override { return pinned; }
+    size_t pinned_bytes() override { return pinned; }
+};
+
+static void test_untrimmable_idle_bytes_fail_instead_of_hanging() {
+    Pinned f;
+    Core c(&f, 300, 2);
+    f.pinned = 250;  // 110 per query no longer fits beside 250
+    bool threw = false;
+    try {
+        c.submit(0, 1, 1);
+    } catch (const AdmissionError &) {
+        threw = true;
+    }
+    CHECK(threw);
+    f.pinned = 0;
+    int64_t a = c.submit(0, 1, 2);
+    Req r;
+    CHECK(c.wait(a, 5.0, r) && r.status == 0);
+    CHECK(c.collect(a));
+    // layouts that appear after submission: the queued queries fail, later ones run
+    Pinned g;
+    g.sleep_ms = 50;
+    Core d(&g, 300, 1);
+    int64_t q1 = d.submit(0, 1, 1);
+    int64_t q2 = d.submit(0, 0, 2), q3 = d.submit(0, 0, 3);
+    std::this_thread::sleep_for(std::chrono::milliseconds(10));
+    g.pinned = 250;  // built while q1 runs
+    CHECK(d.wait(q1, 5.0, r) && r.status == 0);
+    CHECK(d.collect(q1));
+    CHECK(d.wait(q2, 5.0, r) && r.status == kAdmissionStatus);
+    CHECK(d.wait(q3, 5.0, r) && r.status == kAdmissionStatus);
+    CHECK(d.collect(q2) && d.collect(q3));
+    std::puts("ok pinned idle bytes");
+}
+
 int main() {
     test_admission();
     test_batching_and_results();
@@ -218,6 +260,7 @@ int main() {
     test_failed_query_frees_memory();
     test_concurrent_workers_overlap();
     test_idle_bytes_charged_and_trimmed();
+    test_untrimmable_idle_bytes_fail_instead_of_hanging();
     std::puts("ALL OK");
     return 0;
 }

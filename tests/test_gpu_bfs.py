@@ -61,18 +61,27 @@ def test_hybrid_switches_direction():
     assert st.push_iterations >= 1 and st.pull_iterations >= 1
 
 
-@pytest.mark.parametrize("lb", ["vp", "wm", "cm", "etwc"])
-@pytest.mark.parametrize("name", ["rmat12", "grid64", "path100k", "star5000", "single", "cliques"])
+@pytest.mark.parametrize("lb", ["vp", "wm", "cm", "etwc", "strict"])
+@pytest.mark.parametrize("name", ["rmat12", "rmat14", "grid64", "path100k", "star5000", "single", "cliques",
+                                  "isolated7"])
 def test_fused(lb, name):
     st = _run(name, gg.make_schedule(lb=lb, fusion=True))
     assert st.fused == 1
 
 
+@pytest.mark.parametrize("lb", ["vp", "strict"])
 @pytest.mark.parametrize("rep", [gg.REP_BOOLMAP, gg.REP_BITMAP])
-def test_fused_hybrid(rep):
-    s = gg.make_schedule(lb="vp", fusion=True, hybrid={"direction": gg.PULL, "pull_rep": rep}, threshold=0.01)
+def test_fused_hybrid(rep, lb):
+    s = gg.make_schedule(lb=lb, fusion=True, hybrid={"direction": gg.PULL, "pull_rep": rep, "lb": "vp"},
+                         threshold=0.01)
     st = _run("rmat14", s)
     assert st.fused == 1 and st.pull_iterations >= 1
+
+
+def test_fused_strict_every_source_small_graph():
+    g = host_graph("cliques")
+    for s in range(g.n):
+        _run("cliques", gg.make_schedule(lb="strict", fusion=True), src=s)
 
 
 def test_every_source_small_graph():

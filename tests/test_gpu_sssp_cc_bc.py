@@ -12,7 +12,7 @@ from gpu_util import assert_int_equal, dev_graph, host_graph, oracle_bc, oracle_
 pytestmark = pytest.mark.gpu
 
 LBS = ["vp", "wm", "cm", "strict", "twc", "etwc", "edge_only"]
-FUSED_LBS = ["vp", "wm", "cm", "etwc"]
+FUSED_LBS = ["vp", "wm", "cm", "etwc", "strict"]
 GRAPHS = ["rmat12", "grid64", "star5000", "cliques", "isolated7", "single"]
 INF_DELTA = 2**31 - 1
 
