@@ -25,14 +25,7 @@ sys.path.insert(0, ROOT)
 
 
 def _report_exit():
-    # registered before the library is imported, so it runs after the
-    # library's own exit hook has closed every graph and server
     print("bench: library objects closed, interpreter exiting", file=sys.stderr, flush=True)
-
-
-import atexit  # noqa: E402
-
-atexit.register(_report_exit)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, GB/s
 PR_SEGMENT = 1 << 20   # PageRank pull EdgeBlocking: source segments of 2^20 vertices
@@ -955,4 +948,8 @@ def cpu_baseline(g, src, reached_edges, outs, algos):
 
 
 if __name__ == "__main__":
+    import atexit
+    # registered before the library is imported, so it runs after the
+    # library's own exit hook has closed every graph and server
+    atexit.register(_report_exit)
     main()

@@ -1,0 +1,343 @@
+// Runtime support for programs compiled from the algorithm and scheduling
+// languages (the compiler in paper_2012_07990_amd/compiler): generated code
+// defines its edge and vertex functors and a main function, and calls these
+// templates for the operators. A generated module is compiled against these
+// headers and linked with libgg.so (frontier conversions, scans, fills).
+//
+// Edge functors follow the load balancers' interface (lb.hpp): active(x),
+// done(x), load / apply / edge, begin / flush. A PUSH step runs through
+// push_apply with the schedule's load balance, frontier creation and
+// deduplication; a PULL step runs k_gen_pull, one lane per destination that
+// passes the `to` filter, over its in-neighbours in the input frontier, and
+// stops at the first one after which the filter fails (the early exit the
+// GPU Backend section describes for pull traversals).
+//
+// A while-loop scheduled with kernel fusion runs as one persistent
+// cooperative launch (k_gen_fused): the loop state (frontier sizes, the two
+// queues, the round counter) lives in device memory, each round's operator
+// runs as the grid-stride __device__ form of its load balancer, and rounds
+// are separated by the grid barrier of fused.hpp.
+#pragma once
+
+#include "algos.hpp"
+#include "driver.hpp"
+#include "fused.hpp"
+#include "handles.hpp"
+
+namespace gg {
+namespace gen {
+
+// PULL edgeset.apply (from a dense frontier, or every vertex when ALL) over
+// the grid described by t: one lane per destination
+template <int IN_REP, int CREATE, bool ALL, class F>
+__device__ void gen_pull_dev(const DevGraph &g, F &f, const uint8_t *in_bool, const unsigned long long *in_bits,
+                             const OutFrontier &out, Tid t) {
+    __shared__ StageLDS s_st;
+    if (threadIdx.x == 0) s_st.c = 0;
+    __syncthreads();
+    const long long stride = (long long)t.nblocks * kBlock;
+    for (long long base = (long long)t.block * kBlock; base < g.n; base += stride) {
+        const long long v0 = base + threadIdx.x;
+        const int v = (int)v0;
+        bool modified = false;
+        if (v < g.n && f.active(v)) {
+            for (int e = g.in_row_ptr[v]; e < g.in_row_ptr[v + 1]; e++) {
+                const int u = g.in_col[e];
+                bool in = true;
+                if constexpr (!ALL) in = IN_REP == kRepBoolmap ? in_bool[u] != 0 : bit_test(in_bits, u);
+                if (!in) continue;
+                if (f.apply(u, v, e, f.load(u, v, e)) >= 0) modified = true;
+                if (f.done(v)) break;
+            }
+        }
+        if constexpr (CREATE == kCreateFused) {
+            emit_staged<kCreateFused, kDedupNone>(out, s_st, modified, v);
+            emit_flush<kCreateFused>(out, s_st);
+        } else if constexpr (CREATE == kCreateBitmap) {
+            const uint64_t word = __ballot(modified);
+            if (lane_id() == 0 && v0 < ((long long)g.n + 63) / 64 * 64) out.bitmap[v0 >> 6] = word;
+        } else {
+            if (v < g.n) out.boolmap[v] = modified ? 1 : 0;
+        }
+    }
+}
+
+template <int IN_REP, int CREATE, bool ALL, class F>
+__global__ __launch_bounds__(kBlock) void k_gen_pull(DevGraph g, F f, const uint8_t *in_bool,
+                                                     const unsigned long long *in_bits, OutFrontier out) {
+    gen_pull_dev<IN_REP, CREATE, ALL>(g, f, in_bool, in_bits, out, Tid::here());
+}
+
+// vertices.apply(f)
+template <class F>
+__global__ __launch_bounds__(kBlock) void k_gen_vertices(int n, F f) {
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) f(v);
+}
+
+template <class F>
+void vertices_apply(Ctx &c, int n, F f) {
+    hipLaunchKernelGGL(k_gen_vertices<F>, dim3(blocks_for(n, kBlock, 8192)), dim3(kBlock), 0, c.s, n, f);
+    GG_CHECK_LAUNCH();
+    c.launches++;
+}
+
+// fill a vector with a value (a vector's initialiser)
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_gen_fill(T *p, int n, T v) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = v;
+}
+template <class T>
+void fill(Ctx &c, T *p, int n, T v) {
+    hipLaunchKernelGGL(k_gen_fill<T>, dim3(blocks_for(n, kBlock, 8192)), dim3(kBlock), 0, c.s, p, n, v);
+    GG_CHECK_LAUNCH();
+    c.launches++;
+}
+
+// out-degrees (edges.getOutDegrees())
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_gen_outdeg(DevGraph g, T *p) {
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < g.n; v += gridDim.x * kBlock)
+        p[v] = (T)(g.row_ptr[v + 1] - g.row_ptr[v]);
+}
+template <class T>
+void out_degrees(Ctx &c, const DevGraph &g, T *p) {
+    hipLaunchKernelGGL(k_gen_outdeg<T>, dim3(blocks_for(g.n, kBlock, 8192)), dim3(kBlock), 0, c.s, g, p);
+    GG_CHECK_LAUNCH();
+    c.launches++;
+}
+
+// one element written from the host (main's `vec[i] = value;`, and
+// frontier.addVertex(i)); an index outside [0, n) is refused
+template <class T>
+void set_one(Ctx &c, T *p, long long n, int64_t i, T v) {
+    require(i >= 0 && i < n, GG_ERR_INVALID_ARG, "vertex index out of range");
+    GG_HIP(hipMemcpyAsync(p + i, &v, sizeof(T), hipMemcpyHostToDevice, c.s));
+    GG_HIP(hipStreamSynchronize(c.s));
+}
+
+// frontier.addVertex(v) on the live queue
+inline void add_vertex(Ctx &c, FrontierState &fs, int n, int64_t v) {
+    require(v >= 0 && v < n, GG_ERR_INVALID_ARG, "vertex index out of range");
+    set_one<int32_t>(c, fs.queue(), fs.qcap, fs.count, (int32_t)v);
+    fs.count++;
+}
+
+// a frontier holding every vertex (new vertexset{Vertex}(vertices.size()))
+__global__ __launch_bounds__(kBlock) inline void k_gen_iota(int32_t *q, int n) {
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) q[v] = v;
+}
+
+// edges.from(frontier).to(filter).apply...(f) under a SimpleGPUSchedule
+// (the schedule already picked by the hybrid rule); iter numbers the step
+// for monotonic deduplication
+template <class F>
+void frontier_step(Ctx &c, const DevGraph &g, Workspace &ws, FrontierState &fs, const gg_simple_schedule &sc,
+                   F f, int iter) {
+    if (sc.direction == GG_PUSH) {
+        const int32_t *q = fs.as_queue();
+        const int dd = dedup_mode(sc);
+        OutFrontier o = fs.prep_out(sc.frontier_creation, dd, iter);
+        const PushPlan p{sc.load_balance, sc.frontier_creation, dd};
+        push_apply(c, g, ws, p, q, fs.count, f, o, member_map(ws, g.n, p.lb));
+        fs.commit(sc.frontier_creation);
+        return;
+    }
+    const uint8_t *ib = nullptr;
+    const unsigned long long *it = nullptr;
+    if (sc.pull_rep == GG_REP_BITMAP) it = fs.as_bitmap();
+    else ib = fs.as_boolmap();
+    OutFrontier o{};
+    o.overflow = fs.cnt(2);
+    o.count = fs.cnt(0);
+    fill_i32(c, fs.cnt(0), 1, 0);
+    const int create = sc.frontier_creation;
+    if (create == kCreateFused) {
+        o.q = fs.ws.q[fs.qi ^ 1].p;
+        o.cap = (int32_t)fs.qcap;
+    } else if (create == kCreateBoolmap) {
+        o.boolmap = fs.ws.boolmap[fs.bi ^ 1].p;
+    } else {
+        o.bitmap = fs.ws.bitmap[fs.ti ^ 1].p;
+    }
+    const dim3 grid(blocks_for(g.n, kBlock, 16384)), block(kBlock);
+    if (ib) {
+        if (create == kCreateFused) hipLaunchKernelGGL((k_gen_pull<kRepBoolmap, kCreateFused, false, F>), grid, block, 0, c.s, g, f, ib, it, o);
+        else if (create == kCreateBoolmap) hipLaunchKernelGGL((k_gen_pull<kRepBoolmap, kCreateBoolmap, false, F>), grid, block, 0, c.s, g, f, ib, it, o);
+        else hipLaunchKernelGGL((k_gen_pull<kRepBoolmap, kCreateBitmap, false, F>), grid, block, 0, c.s, g, f, ib, it, o);
+    } else {
+        if (create == kCreateFused) hipLaunchKernelGGL((k_gen_pull<kRepBitmap, kCreateFused, false, F>), grid, block, 0, c.s, g, f, ib, it, o);
+        else if (create == kCreateBoolmap) hipLaunchKernelGGL((k_gen_pull<kRepBitmap, kCreateBoolmap, false, F>), grid, block, 0, c.s, g, f, ib, it, o);
+        else hipLaunchKernelGGL((k_gen_pull<kRepBitmap, kCreateBitmap, false, F>), grid, block, 0, c.s, g, f, ib, it, o);
+    }
+    GG_CHECK_LAUNCH();
+    c.launches++;
+    if (create != kCreateFused) {
+        // the dense output's population (a ballot per 64 destinations)
+        fill_i32(c, fs.cnt(0), 1, 0);
+        if (create == kCreateBoolmap) count_boolmap(c, o.boolmap, g.n, fs.cnt(0));
+        else count_bitmap(c, o.bitmap, g.n, fs.cnt(0));
+    }
+    fs.commit_pull(create);
+}
+
+// edges.apply(f) over every edge: PUSH through the schedule's load balancer
+// from a frontier of every vertex (ids = 0..n-1), or PULL over every
+// destination's in-edges
+template <class F>
+void all_edges_step(Ctx &c, const DevGraph &g, Workspace &ws, const int32_t *ids, const gg_simple_schedule &sc,
+                    F f) {
+    if (sc.direction == GG_PUSH) {
+        ws.boolmap[1].ensure(((size_t)g.n + 255) / 256 * 256);
+        OutFrontier o{};
+        o.boolmap = ws.boolmap[1].p;  // nothing is emitted
+        const PushPlan p{sc.load_balance, kCreateBoolmap, kDedupNone};
+        push_apply(c, g, ws, p, ids, g.n, f, o, member_map(ws, g.n, p.lb));
+        return;
+    }
+    OutFrontier o{};
+    ws.boolmap[1].ensure(((size_t)g.n + 255) / 256 * 256);
+    o.boolmap = ws.boolmap[1].p;
+    hipLaunchKernelGGL((k_gen_pull<kRepBoolmap, kCreateBoolmap, true, F>), dim3(blocks_for(g.n, kBlock, 16384)),
+                       dim3(kBlock), 0, c.s, g, f, nullptr, nullptr, o);
+    GG_CHECK_LAUNCH();
+    c.launches++;
+}
+
+
+// ---- kernel fusion: the whole frontier loop in one persistent launch ----------
+
+struct GenFusedArgs {
+    DevGraph g;
+    int32_t *q0, *q1;        // the two queues (q0 holds the first frontier)
+    int32_t *cnt;            // [0..2] rotating frontier sizes, [3] rounds, [4] PULL rounds,
+                             // [8..10] rotating overflow flags
+    int32_t *tags;           // monotonic-counter deduplication
+    int32_t iter0;           // the tag of the round before the loop
+    int32_t cap;             // queue capacity
+    float threshold;         // hybrid: PULL when |F| > threshold * n
+    uint8_t *map_bool;       // PULL input frontier, boolmap form
+    unsigned long long *map_bits;  // PULL input frontier, bitmap form
+    GridBarrier bar;
+    long long *scan, *scan_part;   // STRICT: the frontier's degree scan
+};
+
+// LB: the PUSH load balancer; DD: kDedupNone or kDedupMonotonic; S2: 0 = PUSH
+// only, 1 / 2 = hybrid with a PULL step over a boolmap / bitmap. A round's
+// overflow flag is read at the head of the next round (after the barrier that
+// ends the round that raised it), so every workgroup leaves at the same round.
+template <int LB, int DD, int S2, class FP, class FL>
+__global__ __launch_bounds__(kBlock) void k_gen_fused(GenFusedArgs a, FP fp, FL fl) {
+    const Tid t = Tid::here();
+    const int n = a.g.n;
+    long long ne = 0;
+    GridBarrier bar = a.bar;
+    int32_t *qin = a.q0, *qout = a.q1;
+    int it = 0, pulls = 0;
+    for (;;) {
+        if (it > 0 && load_relaxed(&a.cnt[8 + (it + 2) % 3]) != 0) break;
+        const int cnt = load_relaxed(&a.cnt[it % 3]);
+        if (cnt == 0) break;
+        if (t.block == 0 && threadIdx.x == 0) {
+            __hip_atomic_store(&a.cnt[(it + 2) % 3], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.cnt[8 + (it + 1) % 3], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        OutFrontier o{};
+        o.q = qout;
+        o.count = &a.cnt[(it + 1) % 3];
+        o.cap = a.cap;
+        o.overflow = &a.cnt[8 + it % 3];
+        const bool pull = S2 != 0 && (double)cnt > (double)a.threshold * (double)n;
+        if (!pull) {
+            if constexpr (DD == kDedupMonotonic) {
+                o.tags = a.tags;
+                o.iter = a.iter0 + it + 1;
+            }
+            const SrcQueue src{qin, cnt};
+            if constexpr (LB == GG_LB_VERTEX_BASED) lb_vp<kCreateFused, DD, false>(a.g, src, fp, o, t, ne);
+            else if constexpr (LB == GG_LB_WM) lb_wm<kCreateFused, DD>(a.g, src, fp, o, t, ne);
+            else if constexpr (LB == GG_LB_CM) lb_cm<kCreateFused, DD, false>(a.g, src, fp, o, t, ne);
+            else if constexpr (LB == GG_LB_STRICT) {
+                if (!grid_degree_scan(a.g, src, a.scan, a.scan_part, bar)) break;
+                lb_strict<kCreateFused, DD>(a.g, src, a.scan, fp, o, t, ne);
+            } else lb_etwc<kCreateFused, DD, false>(a.g, src, fp, o, t, ne);
+        } else {
+            pulls++;
+            // dense input map from the queue: clear, barrier, scatter, barrier
+            const long long stride = (long long)t.nblocks * kBlock;
+            const long long gid = (long long)t.block * kBlock + threadIdx.x;
+            if constexpr (S2 == 1) {
+                for (long long i = gid; i < n; i += stride) a.map_bool[i] = 0;
+            } else {
+                for (long long i = gid; i < (n + 63) / 64; i += stride) a.map_bits[i] = 0ull;
+            }
+            if (!grid_sync(bar)) break;
+            for (long long i = gid; i < cnt; i += stride) {
+                const int v = qin[i];
+                if constexpr (S2 == 1) a.map_bool[v] = 1;
+                else atomic_or_u64(&a.map_bits[v >> 6], 1ull << (v & 63));
+            }
+            if (!grid_sync(bar)) break;
+            if constexpr (S2 == 1) gen_pull_dev<kRepBoolmap, kCreateFused, false>(a.g, fl, a.map_bool, nullptr, o, t);
+            else if constexpr (S2 == 2) gen_pull_dev<kRepBitmap, kCreateFused, false>(a.g, fl, nullptr, a.map_bits, o, t);
+        }
+        if (!grid_sync(bar)) break;
+        int32_t *tq = qin;
+        qin = qout;
+        qout = tq;
+        it++;
+    }
+    if (t.block == 0 && threadIdx.x == 0) {
+        a.cnt[3] = it;
+        a.cnt[4] = pulls;
+    }
+}
+
+// Run `while (frontier not empty) frontier = step(frontier)` as one launch
+// from the live frontier of fs; advances iter by the rounds run and leaves fs
+// empty. Throws GG_ERR_OUT_OF_MEMORY when a round's output exceeded the
+// queue (deduplication disabled).
+template <int LB, int DD, int S2, class FP, class FL>
+void fused_loop(Ctx &c, Graph &G, const DevGraph &g, Workspace &ws, FrontierState &fs, float threshold, FP fp,
+                FL fl, int &iter) {
+    static_assert(LB == GG_LB_VERTEX_BASED || LB == GG_LB_WM || LB == GG_LB_CM || LB == GG_LB_STRICT ||
+                      LB == GG_LB_ETWC,
+                  "a fused loop runs VERTEX_BASED, WM, CM, STRICT or ETWC");
+    static_assert(DD == kDedupNone || DD == kDedupMonotonic, "a fused loop deduplicates with monotonic counters");
+    if (fs.count == 0) return;
+    const int32_t *q0 = fs.as_queue();
+    const void *kern = (const void *)k_gen_fused<LB, DD, S2, FP, FL>;
+    const int blocks = fused_grid_for(kern, G, c.num_cus);
+    const long long cap = fs.qcap < 0x7fffffffll ? fs.qcap : 0x7fffffffll;
+    if (LB == GG_LB_STRICT) {
+        ws.scan.ensure((size_t)cap + 1);
+        ws.scan_part.ensure((size_t)blocks);
+    }
+    int32_t *cnt = ws.counters.p + 16;  // the step counters of fs stay below
+    fill_i32(c, cnt, 16, 0);
+    fill_i32(c, cnt, 1, fs.count);
+    GenFusedArgs a{g,
+                   const_cast<int32_t *>(q0),
+                   ws.q[fs.qi ^ 1].p,
+                   cnt,
+                   ws.tags.p,
+                   iter,
+                   (int32_t)cap,
+                   threshold,
+                   ws.boolmap[fs.bi ^ 1].p,
+                   ws.bitmap[fs.ti ^ 1].p,
+                   prepare_barrier(c, ws, blocks),
+                   ws.scan.p,
+                   ws.scan_part.p};
+    void *args[] = {&a, &fp, &fl};
+    launch_cooperative(c, kern, blocks, args);
+    check_barrier(c, ws);
+    GG_HIP(hipMemcpyAsync(ws.h_i32.p, cnt, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
+    GG_HIP(hipStreamSynchronize(c.s));
+    require(ws.h_i32.p[8] == 0 && ws.h_i32.p[9] == 0 && ws.h_i32.p[10] == 0, GG_ERR_OUT_OF_MEMORY,
+            "output frontier exceeded its queue capacity (enable deduplication)");
+    iter += ws.h_i32.p[3];
+    fs.count = 0;
+}
+
+}  // namespace gen
+}  // namespace gg
