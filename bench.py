@@ -30,6 +30,7 @@ def _report_exit():
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, GB/s
 PR_SEGMENT = 1 << 20   # PageRank pull EdgeBlocking: source segments of 2^20 vertices
 PR_LDS_SOURCES = 12288 # highest-degree sources per segment the STRICT kernel keeps in LDS
+CC_SEGMENT = 1 << 20   # CC hook sweep: pairs blocked by destination segments of 2^20 vertices
 
 
 def measured_traffic(kernel_src: str, summary: str, schedule_tag: str):
@@ -99,7 +100,7 @@ def schedules(gg, pr_segment=PR_SEGMENT):
     bfs.s1.load_balance = gg.LB_STRICT
     bfs.threshold = 0.01
     sssp = gg.make_schedule(lb="strict", delta=4096)
-    cc = gg.make_schedule(lb="edge_only")
+    cc = gg.make_schedule(lb="edge_only", edge_blocking=True, blocking_size=CC_SEGMENT)
     pr = gg.make_schedule(lb="strict", direction=gg.PULL, edge_blocking=True, blocking_size=pr_segment)
     bc = gg.schedule_preset(gg.ALGO_BC, gg.PRESET_POWERLAW)
     bc.s1.load_balance = gg.LB_STRICT
@@ -120,6 +121,8 @@ def sweep_schedules(gg):
             s.threshold = th
             out["bfs"]["hybrid-%s-%g" % (lb, th)] = s
     out["cc"]["edge_only"] = gg.make_schedule(lb="edge_only")
+    for N in [1 << 18, 1 << 19, 1 << 20, 1 << 21]:
+        out["cc"]["edge_only-eb-%d" % N] = gg.make_schedule(lb="edge_only", edge_blocking=True, blocking_size=N)
     for th in [0.001, 0.01, 0.05, 0.2]:
         s = gg.schedule_preset(gg.ALGO_BFS, gg.PRESET_BFS_HYBRID)
         s.threshold = th

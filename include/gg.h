@@ -233,7 +233,13 @@ gg_status gg_bfs_noalloc(gg_graph *g, int32_t src, const gg_schedule *s, int32_t
 gg_status gg_sssp(gg_graph *g, int32_t src, const gg_schedule *s, int32_t *dist_dev,
                   gg_stream_t stream, gg_stats *stats);
 /* Connected components (hooking + shortcutting): label_dev[n] int32 = the
-   smallest vertex id of the component. Requires GG_SYMMETRIC. */
+   smallest vertex id of the component. Requires GG_SYMMETRIC. EDGE_ONLY
+   sweeps every undirected edge once per round; with edge_blocking set the
+   sweep runs over that pair list grouped by the segment floor(v /
+   blocking_size) of the larger endpoint (the EdgeBlocking preprocessing
+   applied to this all-edges operator; built on the device once per width
+   and owned by the graph), one launch per segment; at most 64 segments
+   (GG_ERR_UNSUPPORTED_SCHEDULE otherwise). */
 gg_status gg_cc(gg_graph *g, const gg_schedule *s, int32_t *label_dev, gg_stream_t stream,
                 gg_stats *stats);
 

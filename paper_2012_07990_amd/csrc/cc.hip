@@ -7,6 +7,7 @@
 // only decrease and never leave the component, so the fixpoint labels every
 // vertex with the smallest id of its component.
 #include <algorithm>
+#include <vector>
 
 #include "algos.hpp"
 #include "driver.hpp"
@@ -136,6 +137,119 @@ static void ensure_upper(Ctx &c, Graph &G) {
     std::swap(G.upper.n, pairs.n);
 }
 
+// ---- EdgeBlocking of the pair list ---------------------------------------------
+// The hook sweep processes every undirected edge each round, which is where
+// the EdgeBlocking preprocessing applies: the pairs are grouped by the
+// segment floor(v / N) of their larger endpoint, keeping CSR order inside a
+// segment, and each segment is swept by its own launch, so the random label
+// reads of a launch stay inside one segment's labels (and its L2 lines) while
+// the smaller endpoints stream through label[] in ascending order. A stable
+// counting sort on the device: per tile of kPairTile pairs a histogram over
+// the S <= kMaxPairSeg segments, an exclusive scan of the histograms in
+// segment-major order, then each tile scatters its pairs in order, ranking
+// equal segments within a wavefront by matching the six bits of the
+// segment id with ballots.
+constexpr int kPairTile = kBlock * 8;
+constexpr int kMaxPairSeg = 64;
+
+__global__ __launch_bounds__(kBlock) void k_pair_seg_hist(const int2 *pairs, long long np, int N, int S, long long T,
+                                                          int32_t *hist) {
+    __shared__ int h[kMaxPairSeg];
+    for (long long t = blockIdx.x; t < T; t += gridDim.x) {
+        for (int i = threadIdx.x; i < S; i += kBlock) h[i] = 0;
+        __syncthreads();
+        const long long lo = t * kPairTile, hi = lo + kPairTile < np ? lo + kPairTile : np;
+        for (long long i = lo + threadIdx.x; i < hi; i += kBlock) atomicAdd(&h[pairs[i].y / N], 1);
+        __syncthreads();
+        for (int i = threadIdx.x; i < S; i += kBlock) hist[(long long)i * T + t] = h[i];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pair_seg_scatter(const int2 *pairs, long long np, int N, int S,
+                                                             long long T, const int32_t *off, int2 *out) {
+    __shared__ int run[kMaxPairSeg];
+    __shared__ int wcnt[kBlock / kWave][kMaxPairSeg];
+    const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+    for (long long t = blockIdx.x; t < T; t += gridDim.x) {
+        for (int i = tid; i < S; i += kBlock) run[i] = off[(long long)i * T + t];
+        const long long lo = t * kPairTile, hi = lo + kPairTile < np ? lo + kPairTile : np;
+        for (long long base = lo; base < hi; base += kBlock) {
+            const long long i = base + tid;
+            const bool live = i < hi;
+            const int2 p = live ? pairs[i] : make_int2(0, 0);
+            const int s = live ? p.y / N : 0;
+            uint64_t same = __ballot(live);
+#pragma unroll
+            for (int b = 0; b < 6; b++) {
+                const bool bit = (s >> b) & 1;
+                const uint64_t m = __ballot(live && bit);
+                same &= bit ? m : ~m;
+            }
+            const int below = lanes_below(same);
+            for (int k = tid; k < (kBlock / kWave) * S; k += kBlock) wcnt[k / S][k % S] = 0;
+            __syncthreads();
+            if (live && below == 0) wcnt[w][s] = __popcll(same);
+            __syncthreads();
+            if (live) {
+                int pos = run[s] + below;
+                for (int w2 = 0; w2 < w; w2++) pos += wcnt[w2][s];
+                out[pos] = p;
+            }
+            __syncthreads();
+            for (int k = tid; k < S; k += kBlock) {
+                int tot = 0;
+                for (int w2 = 0; w2 < kBlock / kWave; w2++) tot += wcnt[w2][k];
+                run[k] += tot;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// the pair list blocked by segments of N vertices, built once per (graph, N)
+static const BlockedPairs &ensure_upper_blocked(Ctx &c, Graph &G, int32_t N) {
+    {
+        std::lock_guard<std::mutex> lk(G.mu);
+        auto it = G.upper_eb.find(N);
+        if (it != G.upper_eb.end()) return *it->second;
+    }
+    const long long np = G.m_upper;
+    const int S = (int)(((long long)G.n + N - 1) / N);
+    require(S >= 1 && S <= kMaxPairSeg, GG_ERR_UNSUPPORTED_SCHEDULE,
+            "CC EdgeBlocking supports at most 64 segments (blocking_size >= n / 64)");
+    auto b = std::make_unique<BlockedPairs>();
+    b->N = N;
+    b->pairs.ensure((size_t)std::max<long long>(np, 1));
+    b->seg_start.assign((size_t)S + 1, np);
+    if (np > 0) {
+        const long long T = (np + kPairTile - 1) / kPairTile;
+        require((long long)S * T < (1ll << 31) - 1, GG_ERR_INVALID_ARG, "pair list too large");
+        const int hn = (int)(S * T);
+        DevBuf<int32_t> off;
+        DevBuf<long long> part;
+        off.ensure((size_t)hn + 1);
+        part.ensure(exclusive_scan_partials(hn));
+        const unsigned grid = (unsigned)std::min<long long>(T, 8192);
+        hipLaunchKernelGGL(k_pair_seg_hist, dim3(grid), dim3(kBlock), 0, c.s, G.upper.p, np, N, S, T, off.p);
+        GG_CHECK_LAUNCH();
+        exclusive_scan_i32(c, off.p, hn, part.p);
+        hipLaunchKernelGGL(k_pair_seg_scatter, dim3(grid), dim3(kBlock), 0, c.s, G.upper.p, np, N, S, T, off.p,
+                           b->pairs.p);
+        GG_CHECK_LAUNCH();
+        c.launches += 3;
+        std::vector<int32_t> starts((size_t)S);
+        for (int s = 0; s < S; s++)
+            GG_HIP(hipMemcpyAsync(&starts[s], off.p + (size_t)s * T, sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
+        GG_HIP(hipStreamSynchronize(c.s));
+        for (int s = 0; s < S; s++) b->seg_start[s] = starts[s];
+    }
+    std::lock_guard<std::mutex> lk(G.mu);
+    auto &slot = G.upper_eb[N];
+    if (!slot) slot = std::move(b);
+    return *slot;
+}
+
 __global__ __launch_bounds__(kBlock) void k_cc_init(int32_t *label, int32_t *ids, int n) {
     for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
         label[v] = v;
@@ -252,12 +366,22 @@ void cc_run(Graph &G, const gg_schedule &sch, int32_t *label, hipStream_t stream
     if (s.load_balance == GG_LB_EDGE_ONLY && G.symmetric) {
         ensure_upper(c, G);
         const long long np = G.m_upper;
+        // one sweep per segment of the blocked list, else one over the whole list
+        const int2 *pairs = G.upper.p;
+        std::vector<long long> seg{0, np};
+        if (s.edge_blocking) {
+            const BlockedPairs &bp = ensure_upper_blocked(c, G, s.blocking_size);
+            pairs = bp.pairs.p;
+            seg = bp.seg_start;
+        }
         for (;;) {
             fill_i32(c, ws->counters.p, 1, 0);
-            if (np > 0) {
-                hipLaunchKernelGGL(k_cc_hook_pairs, dim3(blocks_for((np + kEdgeBatch - 1) / kEdgeBatch, kBlock, 16384)),
-                                   dim3(kBlock), 0, c.s, G.upper.p, np, CcHook{label, ws->counters.p},
-                                   c.edge_counter);
+            for (size_t k = 0; k + 1 < seg.size(); k++) {
+                const long long cnt = seg[k + 1] - seg[k];
+                if (cnt <= 0) continue;
+                hipLaunchKernelGGL(k_cc_hook_pairs,
+                                   dim3(blocks_for((cnt + kEdgeBatch - 1) / kEdgeBatch, kBlock, 16384)), dim3(kBlock),
+                                   0, c.s, pairs + seg[k], cnt, CcHook{label, ws->counters.p}, c.edge_counter);
                 GG_CHECK_LAUNCH();
                 c.launches++;
             }

@@ -190,6 +190,14 @@ struct PullBlocked {
     DevBuf<int32_t> hcol;                  // col_ptr's layout with cached sources as ~slot
 };
 
+// CC EdgeBlocking: the upper-triangle pair list grouped by destination
+// segment floor(v / N), CSR order kept inside a segment
+struct BlockedPairs {
+    int32_t N = 0;
+    DevBuf<int2> pairs;
+    std::vector<long long> seg_start;  // S + 1 entries
+};
+
 struct Graph {
     int32_t n = 0;
     int64_t m = 0;
@@ -203,6 +211,7 @@ struct Graph {
     int32_t max_degree = 0;
     std::map<int32_t, std::unique_ptr<EdgeBlocked>> eb;  // per blocking size
     std::map<int32_t, std::unique_ptr<PullBlocked>> pull_eb;  // STRICT pull partitions per segment width
+    std::map<int32_t, std::unique_ptr<BlockedPairs>> upper_eb;  // CC pair lists per segment width
     std::map<int, std::pair<gg_schedule, double>> tuned;       // autotuner winners (schedule, ms) per algorithm
     std::map<int, int> placement;                              // measured CPU-or-GPU target per algorithm
     std::mutex mu;

@@ -87,12 +87,19 @@ static void check_simple(const Graph &g, int algo, const gg_simple_schedule &s, 
     // EdgeBlocking applies only when every edge is processed (the edge
     // processing algorithm's note): the topology-driven PageRank sweep.
     if (s.edge_blocking) {
-        if (algo != GG_ALGO_PR) bad("EdgeBlocking applies only to all-edges operators (PageRank)");
+        if (algo != GG_ALGO_PR && algo != GG_ALGO_CC)
+            bad("EdgeBlocking applies only to all-edges operators (PageRank, the CC hook sweep)");
         const bool push_eb = s.load_balance == GG_LB_EDGE_ONLY && s.direction == GG_PUSH;
         const bool pull_eb = s.load_balance == GG_LB_STRICT && s.direction == GG_PULL;
-        if (!push_eb && !pull_eb)
+        if (algo == GG_ALGO_CC) {
+            if (!push_eb || s.kernel_fusion)
+                bad("CC EdgeBlocking runs the unfused EDGE_ONLY sweep over destination segments");
+            if (((long long)g.n + s.blocking_size - 1) / s.blocking_size > 64)
+                bad("CC EdgeBlocking supports at most 64 segments (blocking_size >= n / 64)");
+        } else if (!push_eb && !pull_eb) {
             bad("EdgeBlocking runs EDGE_ONLY in the PUSH direction (destination segments) or STRICT in the "
                 "PULL direction (source segments)");
+        }
     }
     switch (algo) {
     case GG_ALGO_BFS:

@@ -116,6 +116,15 @@ static std::vector<gg_schedule> candidates(const Graph &G, int algo) {
                 s.s1.kernel_fusion = fused;
                 push(s);
             }
+        // the hook sweep over pairs blocked by destination segment
+        for (int lg = 17; lg <= 22; lg++) {
+            if ((1 << lg) >= G.n || ((long long)G.n + (1 << lg) - 1) >> lg > 64) continue;
+            s = default_schedule();
+            s.s1.load_balance = GG_LB_EDGE_ONLY;
+            s.s1.edge_blocking = 1;
+            s.s1.blocking_size = 1 << lg;
+            push(s);
+        }
         break;
     case GG_ALGO_PR:
         for (int lb : {GG_LB_VERTEX_BASED, GG_LB_WM, GG_LB_ETWC, GG_LB_STRICT}) {

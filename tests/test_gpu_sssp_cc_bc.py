@@ -101,6 +101,35 @@ def test_cc_fused(name, lb):
     assert st.fused == 1
 
 
+@pytest.mark.parametrize("name", GRAPHS + ["rmat14", "path100k"])
+@pytest.mark.parametrize("frac", [64, 41, 7, 1, 0.5])
+def test_cc_edge_blocking(name, frac):
+    """EDGE_ONLY over the pair list blocked by destination segment: 64
+    segments, a ragged last segment, few segments, one, and a width past n."""
+    G = dev_graph(name)
+    N = max(1, int(-(-G.n // frac))) if frac >= 1 else 2 * G.n + 1
+    if -(-G.n // N) > 64:
+        N = -(-G.n // 64)
+    st = gg.Stats()
+    lab = G.cc(gg.make_schedule(lb="edge_only", edge_blocking=True, blocking_size=N), stats=st).cpu().numpy()
+    assert_int_equal(lab, oracle_cc(name), "cc blocked N=%d %s" % (N, name))
+    # the blocked list is cached per width: a second run reuses it, same labels
+    lab2 = G.cc(gg.make_schedule(lb="edge_only", edge_blocking=True, blocking_size=N)).cpu().numpy()
+    assert np.array_equal(lab, lab2)
+
+
+def test_cc_edge_blocking_refusals():
+    G = dev_graph("rmat12")
+    with pytest.raises(gg.GGError) as e:  # 4096 segments
+        G.cc(gg.make_schedule(lb="edge_only", edge_blocking=True, blocking_size=1))
+    assert e.value.status == gg.ERR_UNSUPPORTED_SCHEDULE
+    with pytest.raises(gg.GGError) as e:  # blocking needs the EDGE_ONLY sweep
+        G.cc(gg.make_schedule(lb="cm", edge_blocking=True, blocking_size=1024))
+    assert e.value.status == gg.ERR_UNSUPPORTED_SCHEDULE
+    # the graph still answers afterwards
+    assert_int_equal(G.cc(gg.make_schedule(lb="edge_only")).cpu().numpy(), oracle_cc("rmat12"), "cc rmat12")
+
+
 # ---- BC ------------------------------------------------------------------------------
 
 BC_GRAPHS = ["rmat12", "rmat14", "star5000", "cliques", "isolated7", "single", "fullgrid34", "path100k"]
