@@ -31,6 +31,8 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, GB/s
 PR_SEGMENT = 1 << 20   # PageRank pull EdgeBlocking: source segments of 2^20 vertices
 PR_LDS_SOURCES = 12288 # highest-degree sources per segment the STRICT kernel keeps in LDS
 CC_SEGMENT = 1 << 20   # CC hook sweep: pairs blocked by destination segments of 2^20 vertices
+SSSP_SEGMENT = 1 << 21 # SSSP dense rounds: EdgeBlocked COO with destination segments of 2^21 vertices
+SSSP_DENSE = 0.2       # SSSP rounds whose frontier holds more than this share of the vertices are dense
 
 
 def measured_traffic(kernel_src: str, summary: str, schedule_tag: str):
@@ -99,7 +101,9 @@ def schedules(gg, pr_segment=PR_SEGMENT):
     bfs = gg.schedule_preset(gg.ALGO_BFS, gg.PRESET_POWERLAW)
     bfs.s1.load_balance = gg.LB_STRICT
     bfs.threshold = 0.01
-    sssp = gg.make_schedule(lb="strict", delta=4096)
+    sssp = gg.make_schedule(lb="strict", delta=4096, threshold=SSSP_DENSE,
+                            hybrid={"lb": "edge_only", "edge_blocking": 1, "blocking_size": SSSP_SEGMENT,
+                                    "frontier_creation": gg.CREATE_UNFUSED_BOOLMAP})
     cc = gg.make_schedule(lb="edge_only", edge_blocking=True, blocking_size=CC_SEGMENT)
     pr = gg.make_schedule(lb="strict", direction=gg.PULL, edge_blocking=True, blocking_size=pr_segment)
     bc = gg.schedule_preset(gg.ALGO_BC, gg.PRESET_POWERLAW)
@@ -143,6 +147,12 @@ def sweep_schedules(gg):
         out["sssp"]["strict-d%d" % d] = gg.make_schedule(lb="strict", delta=d)
         out["sssp"]["fused-strict-d%d" % d] = gg.make_schedule(lb="strict", delta=d, fusion=True)
     out["cc"]["fused-strict"] = gg.make_schedule(lb="strict", fusion=True)
+    for th in [0.01, 0.05, 0.1, 0.2]:
+        for N in [1 << 20, 1 << 21]:
+            for cr, tag in [(gg.CREATE_FUSED, "q"), (gg.CREATE_UNFUSED_BOOLMAP, "bool")]:
+                out["sssp"]["hybrid-strict-eb%d-%s-%g" % (N, tag, th)] = gg.make_schedule(
+                    lb="strict", delta=4096, threshold=th,
+                    hybrid={"lb": "edge_only", "edge_blocking": 1, "blocking_size": N, "frontier_creation": cr})
     out["sssp"]["strict-d64-nodedup"] = gg.make_schedule(lb="strict", delta=64, dedup=False)
     out["sssp"]["strict-d64-bitmapdedup"] = gg.make_schedule(lb="strict", delta=64, dedup_type=gg.DEDUP_BITMAP)
     for lb in ["vp", "wm", "etwc", "strict"]:
@@ -203,6 +213,10 @@ def main():
     pr_eb_ms = G.prepare_pull_blocking(args.pr_segment) if (not args.only or "pr" in args.only.split(",")) else None
     if pr_eb_ms is not None:
         log("PageRank pull EdgeBlocking layout (N = %d) built in %.2f ms" % (args.pr_segment, pr_eb_ms))
+    # the EdgeBlocked COO (with weights) that SSSP's dense rounds read, likewise
+    sssp_eb_ms = G.prepare_edgeblocking(SSSP_SEGMENT) if (not args.only or "sssp" in args.only.split(",")) else None
+    if sssp_eb_ms is not None:
+        log("SSSP EdgeBlocked COO (N = %d) built in %.2f ms" % (SSSP_SEGMENT, sssp_eb_ms))
     algos = [a for a in ["bfs", "sssp", "cc", "pr", "bc"] if not args.only or a in args.only.split(",")]
     stream = torch.cuda.current_stream()
 
@@ -393,9 +407,12 @@ def main():
                    % args.scale, "n": g.n, "m": g.m, "source": src, "algorithms": algos,
                    "parallelism": "single-gpu"},
         "per_algo": per,
-        "preprocessing": None if pr_eb_ms is None or "pr" not in per else {
-            "pr_pull_edgeblocking_ms": round(pr_eb_ms, 3), "pr_round_ms": round(per["pr"]["ms"] / 20, 4),
-            "in_pr_rounds": round(pr_eb_ms / (per["pr"]["ms"] / 20), 2)},
+        "preprocessing": {
+            **({} if pr_eb_ms is None or "pr" not in per else {
+                "pr_pull_edgeblocking_ms": round(pr_eb_ms, 3), "pr_round_ms": round(per["pr"]["ms"] / 20, 4),
+                "in_pr_rounds": round(pr_eb_ms / (per["pr"]["ms"] / 20), 2)}),
+            **({} if sssp_eb_ms is None else {"sssp_edgeblocked_coo_ms": round(sssp_eb_ms, 1),
+                                              "sssp_segment": SSSP_SEGMENT})},
         "roofline": roof,
         "cpu_baseline": cpu,
         "parity": parity,

@@ -229,6 +229,13 @@ gg_status gg_bfs_noalloc(gg_graph *g, int32_t src, const gg_schedule *s, int32_t
  * Delta-stepping SSSP from src with the schedule's delta (priority-queue
  * schedule, configDelta): dist_dev[n] int32, INT32_MAX when unreachable.
  * Requires weights. GG_ERR_OVERFLOW when a distance would exceed INT32_MAX-1.
+ * A hybrid schedule (HybridGPUSchedule with INPUT_VERTEXSET_SIZE) runs s2 in
+ * the relaxation rounds whose input frontier holds more than threshold * n
+ * vertices and s1 in the others; s1 fixes delta and must be unfused. s2 may
+ * be EDGE_ONLY with edge_blocking: such a round relaxes every edge whose
+ * source is in the frontier, over the EdgeBlocked COO (destination segments
+ * of blocking_size vertices, built once per width with the edges' weights,
+ * as gg_graph_prepare_edgeblocking does), one launch per segment.
  */
 gg_status gg_sssp(gg_graph *g, int32_t src, const gg_schedule *s, int32_t *dist_dev,
                   gg_stream_t stream, gg_stats *stats);

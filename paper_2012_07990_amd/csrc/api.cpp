@@ -77,7 +77,7 @@ size_t Graph::pooled_bytes() {
 size_t Graph::layout_bytes() {
     std::lock_guard<std::mutex> lk(mu);
     size_t b = coo_src.bytes() + upper.bytes() + in_rp.bytes() + in_col.bytes();
-    for (auto &kv : eb) b += kv.second->src.bytes() + kv.second->dst.bytes();
+    for (auto &kv : eb) b += kv.second->src.bytes() + kv.second->dst.bytes() + kv.second->w.bytes();
     for (auto &kv : upper_eb) b += kv.second->pairs.bytes();
     for (auto &kv : pull_eb) {
         const PullBlocked &p = *kv.second;

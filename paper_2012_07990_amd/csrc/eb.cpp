@@ -3,8 +3,9 @@
 // per destination segment floor(dst / N), an exclusive prefix sum gives every
 // segment's start, and a second pass scatters each edge to its segment's
 // cursor -- a stable counting sort, so sources stay ascending inside a
-// segment. Runs once per (graph, N) on the host; the blocked COO is uploaded
-// and owned by the graph. The paper's edge-processing algorithm reads
+// segment. Runs once per (graph, N) on the host; the blocked COO (and, on a
+// weighted graph, the weights in the same order) is uploaded and owned by
+// the graph. The paper's edge-processing algorithm reads
 // segmentStart[segIdx-1] as the start of segment segIdx; here seg_start has
 // S+1 entries and segment s is [seg_start[s], seg_start[s+1]).
 #include <hip/hip_runtime.h>
@@ -25,9 +26,12 @@ double edgeblock_prepare(Ctx &c, Graph &G, int32_t N) {
     const auto t0 = std::chrono::steady_clock::now();
     const int32_t n = G.n;
     const int64_t m = G.m;
+    const bool weighted = G.has_weights && m > 0;
     std::vector<int32_t> rp((size_t)n + 1), col((size_t)m);
+    std::vector<uint32_t> w(weighted ? (size_t)m : 0);
     GG_HIP(hipMemcpyAsync(rp.data(), G.row_ptr.p, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, c.s));
     if (m) GG_HIP(hipMemcpyAsync(col.data(), G.col.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost, c.s));
+    if (weighted) GG_HIP(hipMemcpyAsync(w.data(), G.w.p, sizeof(uint32_t) * m, hipMemcpyDeviceToHost, c.s));
     GG_HIP(hipStreamSynchronize(c.s));
     const int64_t S = ((int64_t)n + N - 1) / N;
     std::vector<long long> count((size_t)S + 1, 0), start((size_t)S + 1, 0);
@@ -39,11 +43,13 @@ double edgeblock_prepare(Ctx &c, Graph &G, int32_t N) {
     }
     std::vector<long long> cursor(start);
     std::vector<int32_t> osrc((size_t)m), odst((size_t)m);
+    std::vector<uint32_t> ow(weighted ? (size_t)m : 0);
     for (int32_t u = 0; u < n; u++) {
         for (int64_t e = rp[u]; e < rp[u + 1]; e++) {
             const long long i = cursor[col[e] / N]++;
             osrc[i] = u;
             odst[i] = col[e];
+            if (weighted) ow[i] = w[e];
         }
     }
     auto b = std::make_unique<EdgeBlocked>();
@@ -54,6 +60,10 @@ double edgeblock_prepare(Ctx &c, Graph &G, int32_t N) {
     if (m) {
         GG_HIP(hipMemcpyAsync(b->src.p, osrc.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, c.s));
         GG_HIP(hipMemcpyAsync(b->dst.p, odst.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, c.s));
+    }
+    if (weighted) {
+        b->w.ensure((size_t)m);
+        GG_HIP(hipMemcpyAsync(b->w.p, ow.data(), sizeof(uint32_t) * m, hipMemcpyHostToDevice, c.s));
     }
     GG_HIP(hipStreamSynchronize(c.s));
     const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -74,9 +84,12 @@ void ensure_transpose(Ctx &c, Graph &G) {
     if (G.in_rp.p) return;
     const int32_t n = G.n;
     const int64_t m = G.m;
+    const bool weighted = G.has_weights && m > 0;
     std::vector<int32_t> rp((size_t)n + 1), col((size_t)m);
+    std::vector<uint32_t> w(weighted ? (size_t)m : 0);
     GG_HIP(hipMemcpyAsync(rp.data(), G.row_ptr.p, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, c.s));
     if (m) GG_HIP(hipMemcpyAsync(col.data(), G.col.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost, c.s));
+    if (weighted) GG_HIP(hipMemcpyAsync(w.data(), G.w.p, sizeof(uint32_t) * m, hipMemcpyDeviceToHost, c.s));
     GG_HIP(hipStreamSynchronize(c.s));
     std::vector<int32_t> irp((size_t)n + 1, 0), icol((size_t)(m > 0 ? m : 1));
     for (int64_t e = 0; e < m; e++) irp[(size_t)col[e] + 1]++;

@@ -170,6 +170,7 @@ struct Workspace {
 // ---- graph ------------------------------------------------------------------------------
 struct EdgeBlocked {
     DevBuf<int32_t> src, dst;
+    DevBuf<uint32_t> w;  // the edges' weights in blocked order (weighted graphs)
     std::vector<long long> seg_start;  // host copy, S + 1 entries
     int32_t seg_vertices = 0;
 };

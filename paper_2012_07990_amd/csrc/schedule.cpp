@@ -87,8 +87,11 @@ static void check_simple(const Graph &g, int algo, const gg_simple_schedule &s, 
     // EdgeBlocking applies only when every edge is processed (the edge
     // processing algorithm's note): the topology-driven PageRank sweep.
     if (s.edge_blocking) {
-        if (algo != GG_ALGO_PR && algo != GG_ALGO_CC)
-            bad("EdgeBlocking applies only to all-edges operators (PageRank, the CC hook sweep)");
+        if (algo != GG_ALGO_PR && algo != GG_ALGO_CC && algo != GG_ALGO_SSSP)
+            bad("EdgeBlocking applies only to all-edges operators (PageRank, the CC hook sweep, SSSP's EDGE_ONLY "
+                "rounds)");
+        if (algo == GG_ALGO_SSSP && (s.load_balance != GG_LB_EDGE_ONLY || s.direction != GG_PUSH || s.kernel_fusion))
+            bad("SSSP EdgeBlocking runs unfused EDGE_ONLY rounds over destination segments");
         const bool push_eb = s.load_balance == GG_LB_EDGE_ONLY && s.direction == GG_PUSH;
         const bool pull_eb = s.load_balance == GG_LB_STRICT && s.direction == GG_PULL;
         if (algo == GG_ALGO_CC) {
@@ -140,7 +143,9 @@ void validate_schedule(const Graph &g, int algo, const gg_schedule &s) {
     if (s.hybrid) {
         if (!(s.threshold > 0.f && s.threshold <= 1.f)) throw Error(GG_ERR_INVALID_ARG, "threshold must be in (0, 1]");
         check_simple(g, algo, s.s2, true);
-        if (algo != GG_ALGO_BFS && algo != GG_ALGO_BC) bad("hybrid (push/pull) schedules apply to BFS and BC");
+        if (algo != GG_ALGO_BFS && algo != GG_ALGO_BC && algo != GG_ALGO_SSSP)
+            bad("hybrid schedules apply to BFS, BC (push/pull) and SSSP (sparse/dense rounds)");
+        if (algo == GG_ALGO_SSSP && s.s1.kernel_fusion) bad("a hybrid SSSP loop runs unfused");
         if (s.s1.kernel_fusion && s.s2.direction == GG_PUSH && s.s2.load_balance != s.s1.load_balance)
             bad("a fused hybrid loop pushes with s1's load balancer");
         if (s.s1.kernel_fusion && algo != GG_ALGO_BFS) bad("fused hybrid loops are available for BFS");

@@ -296,14 +296,99 @@ static void sssp_fused(Ctx &c, Graph &G, Workspace &ws, int32_t src, const gg_si
     if (maybe_overflow) confirm_overflow(c, g, dist, ws.counters.p + 13, ws.h_i32.p);
 }
 
+// Dense rounds over the EdgeBlocked COO (a hybrid schedule's s2 of EDGE_ONLY
+// with EdgeBlocking): every edge of one destination segment whose source is
+// in the input frontier (a bitmap) is relaxed, kEdgeBatch edges per lane in
+// flight. f reads the weights in the blocked order (its w is the layout's).
+// A launch's distance reads and minima stay inside one segment's entries.
+template <int CREATE, int DEDUP>
+__global__ __launch_bounds__(kBlock) void k_sssp_push_blocked(const int32_t *src, const int32_t *dst, long long lo,
+                                                              long long hi, const unsigned long long *member,
+                                                              SsspRelaxT<false> f, OutFrontier out,
+                                                              unsigned long long *ecount) {
+    // queue appends staged per workgroup (one global atomic per flush): a
+    // dense round appends a large share of the graph's vertices
+    __shared__ StageLDS s_st;
+    if (threadIdx.x == 0) s_st.c = 0;
+    __syncthreads();
+    const long long stride = (long long)gridDim.x * kBlock;
+    long long ne = 0;
+    for (long long base = lo + (long long)blockIdx.x * kBlock; base < hi; base += kEdgeBatch * stride) {
+        const long long e0 = base + threadIdx.x;
+        int uu[kEdgeBatch], vv[kEdgeBatch];
+        bool take[kEdgeBatch];
+#pragma unroll
+        for (int b = 0; b < kEdgeBatch; b++) {
+            const long long e = e0 + b * stride;
+            uu[b] = src[e < hi ? e : hi - 1];
+        }
+#pragma unroll
+        for (int b = 0; b < kEdgeBatch; b++) take[b] = e0 + b * stride < hi && bit_test(member, uu[b]);
+#pragma unroll
+        for (int b = 0; b < kEdgeBatch; b++) vv[b] = take[b] ? dst[e0 + b * stride] : 0;
+        SsspRelaxT<false>::Pre pre[kEdgeBatch];
+#pragma unroll
+        for (int b = 0; b < kEdgeBatch; b++)
+            pre[b] = take[b] ? f.load(uu[b], vv[b], (int)(e0 + b * stride)) : SsspRelaxT<false>::Pre{0, 0};
+#pragma unroll
+        for (int b = 0; b < kEdgeBatch; b++) {
+            int x = -1;
+            if (take[b]) {
+                x = f.apply(uu[b], vv[b], (int)(e0 + b * stride), pre[b]);
+                ne++;
+            }
+            emit_staged<CREATE, DEDUP>(out, s_st, x >= 0, x);
+        }
+        emit_flush<CREATE>(out, s_st);
+    }
+    flush_edge_count(ne, ecount);
+}
+
+template <int CREATE, int DEDUP>
+static void launch_blocked(Ctx &c, const EdgeBlocked &eb, const unsigned long long *member,
+                           const SsspRelaxT<false> &f, const OutFrontier &o) {
+    for (size_t sg = 0; sg + 1 < eb.seg_start.size(); sg++) {
+        const long long lo = eb.seg_start[sg], hi = eb.seg_start[sg + 1];
+        if (hi <= lo) continue;
+        hipLaunchKernelGGL((k_sssp_push_blocked<CREATE, DEDUP>),
+                           dim3(blocks_for((hi - lo + kEdgeBatch - 1) / kEdgeBatch, kBlock, 16384)), dim3(kBlock), 0,
+                           c.s, eb.src.p, eb.dst.p, lo, hi, member, f, o, c.edge_counter);
+        GG_CHECK_LAUNCH();
+        c.launches++;
+    }
+}
+
+static void sssp_blocked_step(Ctx &c, const EdgeBlocked &eb, const unsigned long long *member, int create, int dd,
+                              const SsspRelaxT<false> &f, const OutFrontier &o) {
+    if (create == kCreateBoolmap) launch_blocked<kCreateBoolmap, kDedupNone>(c, eb, member, f, o);
+    else if (create == kCreateBitmap) launch_blocked<kCreateBitmap, kDedupNone>(c, eb, member, f, o);
+    else if (dd == kDedupMonotonic) launch_blocked<kCreateFused, kDedupMonotonic>(c, eb, member, f, o);
+    else if (dd == kDedupBitmap) launch_blocked<kCreateFused, kDedupBitmap>(c, eb, member, f, o);
+    else if (dd == kDedupBoolmap) launch_blocked<kCreateFused, kDedupBoolmap>(c, eb, member, f, o);
+    else launch_blocked<kCreateFused, kDedupNone>(c, eb, member, f, o);
+}
+
+static const EdgeBlocked &blocked_layout(Ctx &c, Graph &G, int32_t N) {
+    edgeblock_prepare(c, G, N);
+    std::lock_guard<std::mutex> lk(G.mu);
+    const EdgeBlocked &eb = *G.eb.at(N);
+    require(eb.w.p != nullptr || G.m == 0, GG_ERR_INVALID_ARG, "EdgeBlocked layout has no weights");
+    return eb;
+}
+
 void sssp_run(Graph &G, int32_t src, const gg_schedule &sch, int32_t *dist, hipStream_t stream, gg_stats *st) {
     Ctx c;
     c.s = stream;
     c.num_cus = G.num_cus;
     StatsScope scope(st, c);
     Lease ws(G);
+    // s1 fixes the loop (delta, fusion); a hybrid schedule runs s2 in rounds
+    // whose input frontier holds more than threshold * n vertices
     const gg_simple_schedule &s = sch.s1;
-    if (s.load_balance == GG_LB_EDGE_ONLY) ensure_coo(c, G);
+    const bool hyb = sch.hybrid != 0;
+    if ((s.load_balance == GG_LB_EDGE_ONLY && !s.edge_blocking) ||
+        (hyb && sch.s2.load_balance == GG_LB_EDGE_ONLY && !sch.s2.edge_blocking))
+        ensure_coo(c, G);
     const DevGraph g = G.view();
     const int n = g.n;
     if (s.kernel_fusion) {
@@ -312,7 +397,10 @@ void sssp_run(Graph &G, int32_t src, const gg_schedule &sch, int32_t *dist, hipS
         return;
     }
     const int dd = dedup_mode(s);
-    const long long qcap = dd == kDedupNone ? (long long)n + g.m : (long long)n;
+    const bool nodedup = dd == kDedupNone || (hyb && sch.s2.frontier_creation == GG_CREATE_FUSED &&
+                                             dedup_mode(sch.s2) == kDedupNone);
+    const long long qcap = nodedup ? (long long)n + g.m : (long long)n;
+    const EdgeBlocked *eb = nullptr;
     FrontierState fs(c, *ws, n, qcap);
     ws->tags.ensure(n);
     fill_i32(c, ws->tags.p, n, 0);
@@ -332,20 +420,32 @@ void sssp_run(Graph &G, int32_t src, const gg_schedule &sch, int32_t *dist, hipS
     for (;;) {
         while (fs.count > 0) {
             if (st) { st->vertices_processed += fs.count; st->iterations++; st->push_iterations++; }
+            const gg_simple_schedule &sr = hyb && (double)fs.count > (double)sch.threshold * n ? sch.s2 : s;
+            const int ddr = dedup_mode(sr);
+            if (sr.load_balance == GG_LB_EDGE_ONLY && sr.edge_blocking) {
+                if (eb == nullptr) eb = &blocked_layout(c, G, sr.blocking_size);
+                const unsigned long long *member = fs.as_bitmap();
+                OutFrontier o = fs.prep_out(sr.frontier_creation, ddr, iter++);
+                SsspRelaxT<false> f{dist, eb->w.p, (long long)(k + 1) * delta, farq[fe & 1], ctr + 16 + (fe & 1), n,
+                                    ws->aux_i32[2].p, fe + 1, ctr + 20};
+                sssp_blocked_step(c, *eb, member, sr.frontier_creation, ddr, f, o);
+                fs.commit(sr.frontier_creation);
+                continue;
+            }
             const int32_t *q = fs.as_queue();
-            OutFrontier o = fs.prep_out(s.frontier_creation, dd, iter++);
-            const PushPlan plan{s.load_balance, s.frontier_creation, dd};
-            const int lbm = s.load_balance;
+            OutFrontier o = fs.prep_out(sr.frontier_creation, ddr, iter++);
+            const PushPlan plan{sr.load_balance, sr.frontier_creation, ddr};
+            const int lbm = sr.load_balance;
             if (lbm == GG_LB_STRICT || lbm == GG_LB_CM || lbm == GG_LB_ETWC || lbm == GG_LB_VERTEX_BASED) {
                 SsspRelaxT<true> f{dist, g.w, (long long)(k + 1) * delta, farq[fe & 1], ctr + 16 + (fe & 1), n,
                                    ws->aux_i32[2].p, fe + 1, ctr + 20};
-                push_apply(c, g, *ws, plan, q, fs.count, f, o, member_map(*ws, n, s.load_balance));
+                push_apply(c, g, *ws, plan, q, fs.count, f, o, member_map(*ws, n, sr.load_balance));
             } else {
                 SsspRelax f{dist, g.w, (long long)(k + 1) * delta, farq[fe & 1], ctr + 16 + (fe & 1), n,
                             ws->aux_i32[2].p, fe + 1, ctr + 20};
-                push_apply(c, g, *ws, plan, q, fs.count, f, o, member_map(*ws, n, s.load_balance));
+                push_apply(c, g, *ws, plan, q, fs.count, f, o, member_map(*ws, n, sr.load_balance));
             }
-            fs.commit(s.frontier_creation);
+            fs.commit(sr.frontier_creation);
         }
         GG_HIP(hipMemcpyAsync(ws->h_i32.p, ctr + 16, 6 * sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
         GG_HIP(hipStreamSynchronize(c.s));

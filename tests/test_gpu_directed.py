@@ -97,6 +97,16 @@ def test_directed_sssp(name, sched):
     assert_int_equal(d, oracle.sssp(g.n, g.row_ptr, g.col, g.w, s), "sssp %s %s" % (name, sched))
 
 
+@pytest.mark.parametrize("name", ["drmat12", "dgnp300", "dchain"])
+def test_directed_sssp_hybrid_blocked(name):
+    """Dense rounds over the EdgeBlocked COO of the out-edges."""
+    g, s = host(name), src_of(name)
+    sched = gg.make_schedule(lb="strict", delta=64, threshold=0.01,
+                             hybrid={"lb": "edge_only", "edge_blocking": 1, "blocking_size": 1000})
+    d = dev(name).sssp(s, sched).cpu().numpy()
+    assert_int_equal(d, oracle.sssp(g.n, g.row_ptr, g.col, g.w, s), "sssp hybrid blocked %s" % name)
+
+
 def test_directed_batched_sssp_matches_single_calls():
     name = "drmat12"
     g = host(name)

@@ -32,6 +32,44 @@ def test_sssp_lb(name, lb, delta):
     _sssp(name, gg.make_schedule(lb=lb, delta=delta))
 
 
+def _hybrid_blocked(lb, delta, th, N, create, dedup=True):
+    return gg.make_schedule(lb=lb, delta=delta, threshold=th,
+                            hybrid={"lb": "edge_only", "edge_blocking": 1, "blocking_size": N,
+                                    "frontier_creation": create, "dedup_enable": int(dedup)})
+
+
+HYBRID_BLOCKED = [("strict", 0.01, 1 << 20, gg.CREATE_FUSED, True),
+                  ("etwc", 0.05, 777, gg.CREATE_UNFUSED_BOOLMAP, True),
+                  ("cm", 0.001, 64, gg.CREATE_UNFUSED_BITMAP, True),
+                  ("strict", 0.2, 3, gg.CREATE_FUSED, False)]
+
+
+@pytest.mark.parametrize("name", GRAPHS + ["rmat14", "path100k"])
+@pytest.mark.parametrize("cfg", HYBRID_BLOCKED)
+@pytest.mark.parametrize("delta", [64, 4096])
+def test_sssp_hybrid_blocked(name, cfg, delta):
+    """Sparse rounds with s1's balancer, dense rounds over the EdgeBlocked COO."""
+    lb, th, N, create, dedup = cfg
+    _sssp(name, _hybrid_blocked(lb, delta, th, N, create, dedup))
+
+
+@pytest.mark.parametrize("name", ["rmat12", "grid64", "cliques"])
+def test_sssp_blocked_every_round(name):
+    _sssp(name, gg.make_schedule(lb="edge_only", delta=64, edge_blocking=True, blocking_size=100))
+
+
+def test_sssp_hybrid_refusals():
+    G = dev_graph("rmat12")
+    with pytest.raises(gg.GGError) as e:  # hybrid SSSP loops run unfused
+        s = _hybrid_blocked("strict", 64, 0.05, 1 << 20, gg.CREATE_FUSED)
+        s.s1.kernel_fusion = 1
+        G.sssp(source("rmat12"), s)
+    assert e.value.status == gg.ERR_UNSUPPORTED_SCHEDULE
+    with pytest.raises(gg.GGError) as e:  # EdgeBlocking needs EDGE_ONLY
+        G.sssp(source("rmat12"), gg.make_schedule(lb="cm", edge_blocking=True, blocking_size=64))
+    assert e.value.status == gg.ERR_UNSUPPORTED_SCHEDULE
+
+
 @pytest.mark.parametrize("delta", [1, 8, 64, 512, INF_DELTA])
 @pytest.mark.parametrize("name", ["grid64", "rmat12", "path100k"])
 def test_sssp_delta_invariance(delta, name):
