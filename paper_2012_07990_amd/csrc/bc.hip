@@ -180,7 +180,9 @@ __global__ __launch_bounds__(kBlock) void k_bc_pull(DevGraph g, int32_t *depth, 
             sigma[v] = s_sum[tid];
         }
         emit_staged<kCreateFused, kDedupNone>(out, s_st, found, v);
-        emit_flush<kCreateFused>(out, s_st);
+        // one flush (one atomic on the level's count) per eight tiles
+        if ((base / (gridDim.x * kBlock)) % 8 == 7 || base + gridDim.x * kBlock >= g.n)
+            emit_flush<kCreateFused>(out, s_st);
     }
     flush_edge_count(ne, ecount);
 }
@@ -349,7 +351,7 @@ void bc_run(Graph &G, int32_t src, const gg_schedule &sch, uint64_t *sigma_out, 
                 queue_to_boolmap(c, order + off[L], cnt, ws->boolmap[0].p);
                 bb = ws->boolmap[0].p;
             }
-            const dim3 grid(blocks_for(n, kBlock, 16384));
+            const dim3 grid(blocks_for(n, kBlock * 8, 16384));  // eight tiles per workgroup
             if (bb)
                 hipLaunchKernelGGL(k_bc_pull<kRepBoolmap>, grid, dim3(kBlock), 0, c.s, g, depth, sigma, L + 1, bb, ib,
                                    o, ctr + 3, c.edge_counter);

@@ -59,8 +59,10 @@ __device__ __forceinline__ void bfs_pull_dev(const DevGraph &g, int32_t *depth, 
             if (found) depth[v] = next;
         }
         if constexpr (OUT == kCreateFused) {
+            // the stage holds eight tiles: one flush (one atomic on the queue
+            // count) per eight tiles and at the workgroup's last tile
             emit_staged<kCreateFused, kDedupNone>(out, s_st, found, v);
-            emit_flush<kCreateFused>(out, s_st);
+            if ((base / stride) % 8 == 7 || base + stride >= g.n) emit_flush<kCreateFused>(out, s_st);
         } else {
             const uint64_t word = __ballot(found);
             if constexpr (OUT == kCreateBitmap) {
@@ -223,7 +225,9 @@ void bfs_fused(Ctx &c, Graph &G, Workspace &ws, int32_t src, const gg_schedule &
 template <int IN_REP>
 static void launch_pull(Ctx &c, const DevGraph &g, int32_t *depth, int next, const uint8_t *ib,
                         const unsigned long long *it, const OutFrontier &o, int create) {
-    const dim3 grid(blocks_for(g.n, kBlock, 16384)), block(kBlock);
+    // eight tiles per workgroup: every workgroup adds its count (or flushes its
+    // appends) with one atomic on a single address, and those serialise
+    const dim3 grid(blocks_for(g.n, kBlock * 8, 16384)), block(kBlock);
     if (create == kCreateFused)
         hipLaunchKernelGGL((k_bfs_pull<IN_REP, kCreateFused>), grid, block, 0, c.s, g, depth, next, ib, it, o, c.edge_counter);
     else if (create == kCreateBoolmap)

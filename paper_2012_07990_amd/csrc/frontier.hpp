@@ -152,6 +152,22 @@ __device__ __forceinline__ void emit_flush(const OutFrontier &o, StageLDS &s) {
     if constexpr (CREATE == kCreateFused) stage_flush(Staged{s.q, &s.c, o.q, o.count}, o.cap, o.overflow, &s.base);
 }
 
+// Flush only once the stage is at least half full. Every flush is an atomic
+// on the one queue count shared by the whole grid, and atomics on one
+// address serialise (~11 ns each here): flushing every workgroup iteration
+// made tens of thousands of them per launch. Appends past a full stage fall
+// back to per-wavefront appends; the caller flushes the rest after its loop.
+// Every lane of the workgroup calls this.
+template <int CREATE>
+__device__ __forceinline__ void emit_flush_half(const OutFrontier &o, StageLDS &s) {
+    if constexpr (CREATE == kCreateFused) {
+        __syncthreads();
+        const bool go = s.c >= kStage / 2;
+        __syncthreads();
+        if (go) stage_flush(Staged{s.q, &s.c, o.q, o.count}, o.cap, o.overflow, &s.base);
+    }
+}
+
 // ---- dense-map membership ----------------------------------------------------------
 __device__ __forceinline__ bool bit_test(const unsigned long long *bm, int v) {
     return (bm[v >> 6] >> (v & 63)) & 1ull;

@@ -107,20 +107,32 @@ __global__ __launch_bounds__(kBlock) void k_boolmap_to_queue(const uint8_t *map,
         if ((base / stride) % 8 == 7 || base + stride >= n) emit_flush<kCreateFused>(o, s_st);
     }
 }
-// one lane per 64-bit word: each lane writes its word's set bits in order
+// one lane per 64-bit word: each lane writes its word's set bits in order;
+// one atomic on the queue count per workgroup tile (atomics on one address
+// serialise)
 __global__ __launch_bounds__(kBlock) void k_bitmap_to_queue(const unsigned long long *map, int nwords,
                                                             int32_t *q, int32_t *count) {
+    __shared__ int s_w[kBlock / kWave], s_base;
+    const int wib = threadIdx.x / kWave;
     const long long stride = (long long)gridDim.x * kBlock;
-    const long long nr = ((long long)nwords + kWave - 1) / kWave * kWave;
-    for (long long wi = (long long)blockIdx.x * kBlock + threadIdx.x; wi < nr; wi += stride) {
+    for (long long b0 = (long long)blockIdx.x * kBlock; b0 < nwords; b0 += stride) {
+        const long long wi = b0 + threadIdx.x;
         unsigned long long word = wi < nwords ? map[wi] : 0ull;
         const int cnt = __popcll(word);
         const int incl = wave_incl_scan(cnt);
-        const int total = wave_bcast(incl, kWave - 1);
-        int base = 0;
-        if (lane_id() == 0 && total) base = atomic_add_i32(count, total);
-        base = wave_bcast(base, 0);
-        int pos = base + incl - cnt;
+        if (lane_id() == kWave - 1) s_w[wib] = incl;
+        __syncthreads();
+        int before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / kWave; w++) {
+            const int x = s_w[w];
+            before += w < wib ? x : 0;
+            total += x;
+        }
+        if (threadIdx.x == 0) s_base = total ? atomic_add_i32(count, total) : 0;
+        __syncthreads();
+        int pos = s_base + before + incl - cnt;
+        __syncthreads();  // s_w and s_base are rewritten by the next tile
         while (word) {
             const int b = __ffsll(word) - 1;
             q[pos++] = (int)(wi * 64 + b);
@@ -129,7 +141,9 @@ __global__ __launch_bounds__(kBlock) void k_bitmap_to_queue(const unsigned long 
     }
 }
 void boolmap_to_queue(Ctx &c, const uint8_t *map, int n, int32_t *q, int32_t *count) {
-    hipLaunchKernelGGL(k_boolmap_to_queue, dim3(blocks_for(n, kBlock, 16384)), dim3(kBlock), 0, c.s, map, n, q,
+    // few workgroups, each flushing its staged appends every 8 tiles: the
+    // flushes' atomics on the one queue count serialise
+    hipLaunchKernelGGL(k_boolmap_to_queue, dim3(blocks_for(n, kBlock * 8, 1024)), dim3(kBlock), 0, c.s, map, n, q,
                        count);
     GG_CHECK_LAUNCH();
     c.launches++;
@@ -143,33 +157,59 @@ void bitmap_to_queue(Ctx &c, const unsigned long long *map, int n, int32_t *q, i
 }
 
 // ---- population counts ---------------------------------------------------------------------
+// One atomic per workgroup on the shared count: atomics on one address
+// serialise, and one per wavefront (16K for a 4M-vertex boolmap) made a count
+// take ~190 us.
+__device__ __forceinline__ void block_add_count(int local, int32_t *count) {
+    __shared__ int s_w[kBlock / kWave];
+    local = wave_sum(local);
+    if (lane_id() == 0) s_w[threadIdx.x / kWave] = local;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / kWave; w++) t += s_w[w];
+        if (t) atomic_add_i32(count, t);
+    }
+}
+
+// non-zero bytes of a 32-bit word
+__device__ __forceinline__ int nonzero_bytes(unsigned x) {
+    const unsigned zero = ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x | 0x7F7F7F7Fu);  // 0x80 per zero byte
+    return 4 - __popc(zero);
+}
+
+// 16 bytes per lane when the map is 16-byte aligned, the tail byte by byte
 __global__ __launch_bounds__(kBlock) void k_count_boolmap(const uint8_t *map, int n, int32_t *count) {
     const long long stride = (long long)gridDim.x * kBlock;
-    const long long nr = ((long long)n + kWave - 1) / kWave * kWave;
+    const long long gid = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const long long nq = (reinterpret_cast<uintptr_t>(map) & 15) == 0 ? n / 16 : 0;
     int local = 0;
-    for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < nr; v += stride)
-        local += (v < n && map[v]) ? 1 : 0;
-    local = wave_sum(local);
-    if (lane_id() == 0 && local) atomic_add_i32(count, local);
+    const uint4 *m4 = reinterpret_cast<const uint4 *>(map);
+    for (long long i = gid; i < nq; i += stride) {
+        const uint4 x = m4[i];
+        local += nonzero_bytes(x.x) + nonzero_bytes(x.y) + nonzero_bytes(x.z) + nonzero_bytes(x.w);
+    }
+    for (long long v = nq * 16 + gid; v < n; v += stride) local += map[v] ? 1 : 0;
+    block_add_count(local, count);
 }
 __global__ __launch_bounds__(kBlock) void k_count_bitmap(const unsigned long long *map, int nwords,
                                                          int32_t *count) {
     const long long stride = (long long)gridDim.x * kBlock;
-    const long long nr = ((long long)nwords + kWave - 1) / kWave * kWave;
     int local = 0;
-    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < nr; i += stride)
-        local += i < nwords ? __popcll(map[i]) : 0;
-    local = wave_sum(local);
-    if (lane_id() == 0 && local) atomic_add_i32(count, local);
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < nwords; i += stride)
+        local += __popcll(map[i]);
+    block_add_count(local, count);
 }
 void count_boolmap(Ctx &c, const uint8_t *map, int n, int32_t *count) {
-    hipLaunchKernelGGL(k_count_boolmap, dim3(blocks_for(n, kBlock, 4096)), dim3(kBlock), 0, c.s, map, n, count);
+    hipLaunchKernelGGL(k_count_boolmap, dim3(blocks_for(((long long)n + 15) / 16, kBlock, 1024)), dim3(kBlock), 0,
+                       c.s, map, n, count);
     GG_CHECK_LAUNCH();
     c.launches++;
 }
 void count_bitmap(Ctx &c, const unsigned long long *map, int n, int32_t *count) {
     const int nwords = (n + 63) / 64;
-    hipLaunchKernelGGL(k_count_bitmap, dim3(blocks_for(nwords, kBlock, 4096)), dim3(kBlock), 0, c.s, map,
+    hipLaunchKernelGGL(k_count_bitmap, dim3(blocks_for(nwords, kBlock, 1024)), dim3(kBlock), 0, c.s, map,
                        nwords, count);
     GG_CHECK_LAUNCH();
     c.launches++;

@@ -52,7 +52,7 @@ __device__ void gen_pull_dev(const DevGraph &g, F &f, const uint8_t *in_bool, co
         }
         if constexpr (CREATE == kCreateFused) {
             emit_staged<kCreateFused, kDedupNone>(out, s_st, modified, v);
-            emit_flush<kCreateFused>(out, s_st);
+            if ((base / stride) % 8 == 7 || base + stride >= g.n) emit_flush<kCreateFused>(out, s_st);
         } else if constexpr (CREATE == kCreateBitmap) {
             const uint64_t word = __ballot(modified);
             if (lane_id() == 0 && v0 < ((long long)g.n + 63) / 64 * 64) out.bitmap[v0 >> 6] = word;
@@ -159,7 +159,7 @@ void frontier_step(Ctx &c, const DevGraph &g, Workspace &ws, FrontierState &fs, 
     } else {
         o.bitmap = fs.ws.bitmap[fs.ti ^ 1].p;
     }
-    const dim3 grid(blocks_for(g.n, kBlock, 16384)), block(kBlock);
+    const dim3 grid(blocks_for(g.n, kBlock * 8, 16384)), block(kBlock);
     if (ib) {
         if (create == kCreateFused) hipLaunchKernelGGL((k_gen_pull<kRepBoolmap, kCreateFused, false, F>), grid, block, 0, c.s, g, f, ib, it, o);
         else if (create == kCreateBoolmap) hipLaunchKernelGGL((k_gen_pull<kRepBoolmap, kCreateBoolmap, false, F>), grid, block, 0, c.s, g, f, ib, it, o);
@@ -197,7 +197,7 @@ void all_edges_step(Ctx &c, const DevGraph &g, Workspace &ws, const int32_t *ids
     OutFrontier o{};
     ws.boolmap[1].ensure(((size_t)g.n + 255) / 256 * 256);
     o.boolmap = ws.boolmap[1].p;
-    hipLaunchKernelGGL((k_gen_pull<kRepBoolmap, kCreateBoolmap, true, F>), dim3(blocks_for(g.n, kBlock, 16384)),
+    hipLaunchKernelGGL((k_gen_pull<kRepBoolmap, kCreateBoolmap, true, F>), dim3(blocks_for(g.n, kBlock * 8, 16384)),
                        dim3(kBlock), 0, c.s, g, f, nullptr, nullptr, o);
     GG_CHECK_LAUNCH();
     c.launches++;

@@ -90,10 +90,11 @@ __device__ void lb_vp(const DevGraph &g, const Src &src, F &f, const OutFrontier
             }
         }
         if constexpr (STAGE) {
-            emit_flush<CREATE>(out, s_st);
+            emit_flush_half<CREATE>(out, s_st);
             f.flush();
         }
     }
+    if constexpr (STAGE) emit_flush<CREATE>(out, s_st);
 }
 
 // owner of edge rank j: the last k in [0, len) with scan[k] <= j
@@ -197,10 +198,11 @@ __device__ void lb_cm(const DevGraph &g, const Src &src, F &f, const OutFrontier
         }
         __syncthreads();
         if constexpr (STAGE) {
-            emit_flush<CREATE>(out, s_st);
+            emit_flush_half<CREATE>(out, s_st);
             f.flush();
         }
     }
+    if constexpr (STAGE) emit_flush<CREATE>(out, s_st);
 }
 
 // ---------------------------------------------------------------------------- ETWC
@@ -294,10 +296,11 @@ __device__ void lb_etwc(const DevGraph &g, const Src &src, F &f, const OutFronti
         }
         __syncthreads();
         if constexpr (STAGE) {
-            emit_flush<CREATE>(out, s_st);
+            emit_flush_half<CREATE>(out, s_st);
             f.flush();
         }
     }
+    if constexpr (STAGE) emit_flush<CREATE>(out, s_st);
 }
 
 // ---------------------------------------------------------------------------- TWC
@@ -477,10 +480,11 @@ __device__ void lb_strict(const DevGraph &g, const Src &src, const long long *sc
                 for (int k = 0; k < kEdgeBatch; k++) emit_staged<CREATE, DEDUP>(out, s_st, xx[k] >= 0, xx[k]);
             }
             __syncthreads();
-            emit_flush<CREATE>(out, s_st);
+            emit_flush_half<CREATE>(out, s_st);
             f.flush();
         }
     }
+    emit_flush<CREATE>(out, s_st);
 }
 
 // ---------------------------------------------------------------------------- EDGE_ONLY

@@ -241,7 +241,7 @@ __device__ __forceinline__ void ms_far_min(const MsSsspArgs &a, const int32_t *f
         const int o = __shfl_xor(local, off, kWave);
         local = o < local ? o : local;
     }
-    if (lane_id() == 0 && local != INT_MAX) atomic_min_i32(kmin, local);
+    if (lane_id() == 0 && local != INT_MAX && local < load_relaxed(kmin)) atomic_min_i32(kmin, local);
 }
 
 // far bits of bucket knew -> near set; later buckets stay; settled ones are dropped

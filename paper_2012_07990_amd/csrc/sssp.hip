@@ -117,7 +117,9 @@ __device__ __forceinline__ void far_min_dev(const int32_t *farq, int fc, const i
         const int o = __shfl_xor(local, off, kWave);
         local = o < local ? o : local;
     }
-    if (lane_id() == 0 && local != INT_MAX) atomic_min_i32(kmin, local);
+    // a plain read first: once a small bucket index is in, most wavefronts
+    // skip the atomic (atomics on one address serialise)
+    if (lane_id() == 0 && local != INT_MAX && local < load_relaxed(kmin)) atomic_min_i32(kmin, local);
 }
 
 // far entries of bucket knew -> near queue; later buckets -> the next far queue
@@ -339,8 +341,9 @@ __global__ __launch_bounds__(kBlock) void k_sssp_push_blocked(const int32_t *src
             }
             emit_staged<CREATE, DEDUP>(out, s_st, x >= 0, x);
         }
-        emit_flush<CREATE>(out, s_st);
+        emit_flush_half<CREATE>(out, s_st);
     }
+    emit_flush<CREATE>(out, s_st);
     flush_edge_count(ne, ecount);
 }
 
@@ -454,7 +457,7 @@ void sssp_run(Graph &G, int32_t src, const gg_schedule &sch, int32_t *dist, hipS
         const int fc = ws->h_i32.p[fe & 1];
         if (fc == 0) break;
         fill_i32(c, ctr + 18, 1, INT_MAX);
-        hipLaunchKernelGGL(k_far_min, dim3(blocks_for(fc, kBlock, 4096)), dim3(kBlock), 0, c.s, farq[fe & 1],
+        hipLaunchKernelGGL(k_far_min, dim3(blocks_for(fc, kBlock * 4, 1024)), dim3(kBlock), 0, c.s, farq[fe & 1],
                            ctr + 16 + (fe & 1), dist, delta, k, ctr + 18);
         GG_CHECK_LAUNCH();
         c.launches++;
@@ -463,7 +466,7 @@ void sssp_run(Graph &G, int32_t src, const gg_schedule &sch, int32_t *dist, hipS
         fill_i32(c, ctr + 16 + ((fe + 1) & 1), 1, 0);
         OutFrontier o = fs.prep_out(kCreateFused, kDedupMonotonic, iter++);
         o.tags = ws->tags.p;
-        hipLaunchKernelGGL(k_far_split, dim3(blocks_for(fc, kBlock, 4096)), dim3(kBlock), 0, c.s, farq[fe & 1],
+        hipLaunchKernelGGL(k_far_split, dim3(blocks_for(fc, kBlock * 8, 1024)), dim3(kBlock), 0, c.s, farq[fe & 1],
                            ctr + 16 + (fe & 1), dist, delta, knew, o, farq[(fe + 1) & 1], ctr + 16 + ((fe + 1) & 1), n,
                            ws->aux_i32[2].p, fe + 2, ctr + 20);
         GG_CHECK_LAUNCH();
