@@ -214,6 +214,17 @@ VARIANTS = {
     SimpleGPUSchedule s1;
     s1.configLoadBalance(CM);
     program->applyGPUSchedule("s1", s1);"""),
+    "bfs_rounds": ("bfs_rounds.gt", ["parent", "seen", "info"], None),
+    "bfs_rounds_fused": ("bfs_rounds.gt", ["parent", "seen", "info"], """
+    SimpleGPUSchedule s0;
+    s0.configKernelFusion(ENABLED);
+    program->applyGPUSchedule("s0", s0);
+    SimpleGPUSchedule s1;
+    s1.configLoadBalance(STRICT);
+    SimpleGPUSchedule s2;
+    s2.configDirection(PULL, BITMAP);
+    HybridGPUSchedule h1(INPUT_VERTEXSET_SIZE, 0.05, s1, s2);
+    program->applyGPUSchedule("s1", h1);"""),
     "pagerank_pull": ("pagerank.gt", ["old_rank"], None),
     "pagerank_push_strict": ("pagerank.gt", ["old_rank"], """
     SimpleGPUSchedule s1;

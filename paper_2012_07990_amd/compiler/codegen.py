@@ -334,6 +334,7 @@ class MainGen:
     def __init__(self, prog: Program, scheds: Dict[str, dict], notes: List[str]):
         self.prog, self.scheds, self.notes = prog, scheds, notes
         self.functors: Dict[str, str] = {}   # C++ name -> definition
+        self.fused_kernels: List[str] = []   # persistent kernels of fused loops
         self.host_vars: Dict[str, str] = {}
         self.frontiers: Dict[str, str] = {}  # program name -> "fs"
         self.labels_used: List[str] = []
@@ -418,7 +419,7 @@ class MainGen:
                 if ty[0] == "scalar":
                     cname = "h_" + name
                     self.host_vars[name] = cname
-                    self.emit("const int64_t %s = %s;" % (cname, self.hexpr(init)), depth)
+                    self.emit("int64_t %s = %s;" % (cname, self.hexpr(init) if init is not None else "0"), depth)
                 elif ty[0] == "vertexset":
                     if init is None:
                         raise CompileError("line %d: a vertexset variable needs an initial value" % line)
@@ -443,7 +444,9 @@ class MainGen:
                     raise CompileError("line %d: unsupported variable type %r" % (line, ty))
             elif k == "assign":
                 _, op, lhs, rhs, label, line = st
-                if lhs[0] == "index" and lhs[1][0] == "id" and lhs[1][1] in self.prog.vectors and op == "=":
+                if lhs[0] == "id" and lhs[1] in self.host_vars and op in ("=", "+="):
+                    self.emit("%s %s %s;" % (self.host_vars[lhs[1]], op, self.hexpr(rhs)), depth)
+                elif lhs[0] == "index" and lhs[1][0] == "id" and lhs[1][1] in self.prog.vectors and op == "=":
                     vec = lhs[1][1]
                     ct = CTYPE[self.prog.vectors[vec]["type"]]
                     self.emit("gen::set_one<%s>(c, vec_%s.p, g.n, (int64_t)(%s), (%s)(%s));"
@@ -459,17 +462,14 @@ class MainGen:
                         and cond[2][2] == "getVertexSetSize" and cond[2][1][0] == "id"
                         and cond[2][1][1] in self.frontiers):
                     raise CompileError("line %d: while (frontier.getVertexSetSize() != 0) is the supported loop" % line)
-                op = wbody[0] if wbody and wbody[0][0] == "var" and wbody[0][2] == ("vertexset",) else None
+                ops = [j for j, x in enumerate(wbody) if x[0] == "var" and x[2] == ("vertexset",)]
+                op = wbody[ops[0]] if len(ops) == 1 else None
                 wsched = self.scheds.get(label) if label else None
                 osched = self.scheds.get(op[4]) if op is not None and op[4] else None
                 if (wsched and wsched["s1"]["kernel_fusion"]) or (osched and osched["s1"]["kernel_fusion"]):
-                    if op is None or op[3] is None or len(wbody) != 3:
-                        raise CompileError("line %d: a fused loop holds the frontier operator and the frontier "
-                                           "swap only" % line)
-                    self.frontier_op(op[1], op[3], op[4] if osched else label, op[5], depth, wbody, 0,
-                                     fused=True)
-                    self.notes.append("while loop at line %d: kernel fusion -> one persistent launch for "
-                                      "every round" % line)
+                    if op is None or op[3] is None:
+                        raise CompileError("line %d: a fused loop holds one frontier operator" % line)
+                    self.fused_while(wbody, ops[0], op[4] if osched else label, line, depth)
                 else:
                     self.emit("while (fs.count > 0) {", depth)
                     self.stmts(wbody, depth + 1)
@@ -487,6 +487,125 @@ class MainGen:
             else:
                 raise CompileError("unsupported statement %r" % (k,))
             i += 1
+
+    def dexpr(self, e) -> str:
+        """A scalar expression inside a fused loop: hoisted locals of main and literals."""
+        k = e[0]
+        if k == "num":
+            return e[1]
+        if k == "bool":
+            return "1" if e[1] else "0"
+        if k == "id" and e[1] in self.host_vars:
+            return self.host_vars[e[1]]
+        if k == "bin":
+            return "(%s %s %s)" % (self.dexpr(e[2]), e[1], self.dexpr(e[3]))
+        if k == "un":
+            return "(%s%s)" % (e[1], self.dexpr(e[2]))
+        raise CompileError("inside a fused loop a scalar statement reads main's local variables and literals "
+                           "only (%r)" % (e,))
+
+    def fused_while(self, wbody, i_op, label, line, depth):
+        """A fused loop (the GPU Backend section's kernel fusion): one generated
+        persistent kernel runs the loop; main's local variables the body uses are
+        hoisted to device memory (copied in before the launch, out after); scalar
+        statements run in every lane alike, vertices.apply over the grid between
+        grid barriers, the operator through the runtime's fused step."""
+        op = wbody[i_op]
+        pre, post = wbody[:i_op], wbody[i_op + 3:]
+        if not pre and not post:
+            # the operator and the swap alone: the runtime's fused loop kernel
+            self.frontier_op(op[1], op[3], label, op[5], depth, wbody, i_op, fused=True)
+            self.notes.append("while loop at line %d: kernel fusion -> one persistent launch for every round"
+                              % line)
+            return
+        hoisted: List[str] = []
+        applies: List[str] = []
+        code_pre: List[str] = []
+        code_post: List[str] = []
+
+        def use(name):
+            if name not in hoisted:
+                hoisted.append(name)
+
+        def walk(e):
+            if isinstance(e, tuple):
+                if e[0] == "id" and e[1] in self.host_vars:
+                    use(e[1])
+                for x in e[1:]:
+                    walk(x)
+
+        for where, stmts_, code in (("pre", pre, code_pre), ("post", post, code_post)):
+            for st in stmts_:
+                if st[0] == "assign" and st[2][0] == "id" and st[2][1] in self.host_vars and st[1] in ("=", "+="):
+                    use(st[2][1])
+                    walk(st[3])
+                    code.append("%s %s %s;" % (self.host_vars[st[2][1]], st[1], self.dexpr(st[3])))
+                elif (st[0] == "expr" and st[1][0] == "method" and st[1][2] == "apply"
+                      and st[1][1] == ("id", self.prog.vertices)):
+                    cname = self.vertex_functor_for(st[1][3][0][1])
+                    k = len(applies)
+                    applies.append(cname)
+                    if where == "pre":
+                        code.append("gen::fused_vertices(a.g.n, vf%d, s.t);" % k)
+                        code.append("if (!grid_sync(s.bar)) break;")
+                    else:
+                        code.append("if (!grid_sync(s.bar)) break;")
+                        code.append("gen::fused_vertices(a.g.n, vf%d, s.t);" % k)
+                elif st[0] == "delete":
+                    raise CompileError("line %d: in a fused loop `delete` belongs to the frontier swap" % st[-1])
+                else:
+                    raise CompileError("line %d: this statement cannot run inside a fused loop (scalar "
+                                       "assignments, vertices.apply and the frontier operator can)" % st[-1])
+        # the operator (checks its form and the swap that follows it) and its template arguments
+        out_name = op[1]
+        kid = len(self.fused_kernels)
+        lb, dd, s2, th = self.fused_params(label, op[5])
+        push, pull = self.frontier_op(out_name, op[3], label, op[5], depth, wbody, i_op, fused=None)
+        kname = "k_fused_%d" % kid
+        params = ["gen::GenFusedArgs a", "%s fp" % push, "%s fl" % pull, "int64_t *hoist"]
+        params += ["%s vf%d" % (cn, k) for k, cn in enumerate(applies)]
+        body = ["    gen::FusedLoopState s = gen::fused_begin(a);"]
+        body += ["    int64_t %s = hoist[%d];" % (self.host_vars[h], j) for j, h in enumerate(hoisted)]
+        body += ["    for (;;) {",
+                 "        const int cnt = gen::fused_round_head(a, s);",
+                 "        if (cnt < 0) break;"]
+        body += ["        " + x for x in code_pre]
+        body += ["        if (!gen::fused_step<%s, %s, %d>(a, fp, fl, s, cnt)) break;" % (lb, dd, s2)]
+        body += ["        " + x for x in code_post]
+        body += ["        if (!gen::fused_round_tail(s)) break;", "    }", "    gen::fused_end(a, s);"]
+        if hoisted:
+            body += ["    if (blockIdx.x == 0 && threadIdx.x == 0) {"]
+            body += ["        hoist[%d] = %s;" % (j, self.host_vars[h]) for j, h in enumerate(hoisted)]
+            body += ["    }"]
+        self.fused_kernels.append("__global__ __launch_bounds__(kBlock) void %s(%s) {\n%s\n}\n"
+                                  % (kname, ", ".join(params), "\n".join(body)))
+        nh = max(len(hoisted), 1)
+        init = self.init_list(True)
+        host = ["if (fs.count > 0) {",
+                "    DevBuf<int64_t> hoist;",
+                "    hoist.ensure(%d);" % nh,
+                "    int64_t hh[%d] = {%s};" % (nh, ", ".join(self.host_vars[h] for h in hoisted) or "0"),
+                "    GG_HIP(hipMemcpyAsync(hoist.p, hh, sizeof(hh), hipMemcpyHostToDevice, c.s));",
+                "    GG_HIP(hipStreamSynchronize(c.s));",
+                "    const void *kern = (const void *)%s;" % kname,
+                "    gen::FusedLaunch L = gen::fused_prepare(c, G, g, *ws, fs, %s, kern, %s, iter);"
+                % (float_literal(th), "true" if lb == "GG_LB_STRICT" else "false"),
+                "    %s fp%s;" % (push, init),
+                "    %s fl%s;" % (pull, init),
+                "    int64_t *hp = hoist.p;"]
+        host += ["    %s vf%d%s;" % (cn, k, self.init_list(False)) for k, cn in enumerate(applies)]
+        host += ["    void *args[] = {%s};" % ", ".join(["&L.a", "&fp", "&fl", "&hp"] +
+                                                      ["&vf%d" % k for k in range(len(applies))]),
+                 "    launch_cooperative(c, kern, L.blocks, args);",
+                 "    gen::fused_complete(c, *ws, fs, iter);",
+                 "    GG_HIP(hipMemcpyAsync(hh, hoist.p, sizeof(hh), hipMemcpyDeviceToHost, c.s));",
+                 "    GG_HIP(hipStreamSynchronize(c.s));"]
+        host += ["    %s = hh[%d];" % (self.host_vars[h], j) for j, h in enumerate(hoisted)]
+        host += ["}"]
+        for x in host:
+            self.emit(x, depth)
+        self.notes.append("while loop at line %d: kernel fusion -> %s, one persistent launch for every round%s"
+                          % (line, kname, "; hoisted to device memory: " + ", ".join(hoisted) if hoisted else ""))
 
     def frontier_op(self, out_name, e, label, line, depth, body, i, fused=False):
         # edges.from(F)[.to(FILT)].applyModified(U, VEC, true)
@@ -521,6 +640,8 @@ class MainGen:
         w = self.prog.edges["weighted"]
         if w is False and any(p for p in self.prog.funcs[udf].params[2:]):
             raise CompileError("line %d: %s takes a weight but the edgeset is unweighted" % (line, udf))
+        if fused is None:
+            return push, pull
         if fused:
             lb, dd, s2, th = self.fused_params(label, line)
             self.emit("gen::fused_loop<%s, %s, %d>(c, G, g, *ws, fs, %s, %s%s, %s%s, iter);"
@@ -659,5 +780,5 @@ extern "C" gg_status gen_main(gg_graph *gh, const int64_t *args, int32_t nargs, 
         return GG_ERR_DEVICE;
     }
 }
-""" % ("\n".join(mg.functors.values()), body)
+""" % ("\n".join(list(mg.functors.values()) + mg.fused_kernels), body)
     return src, notes

@@ -221,94 +221,140 @@ struct GenFusedArgs {
     long long *scan, *scan_part;   // STRICT: the frontier's degree scan
 };
 
-// LB: the PUSH load balancer; DD: kDedupNone or kDedupMonotonic; S2: 0 = PUSH
-// only, 1 / 2 = hybrid with a PULL step over a boolmap / bitmap. A round's
-// overflow flag is read at the head of the next round (after the barrier that
-// ends the round that raised it), so every workgroup leaves at the same round.
-template <int LB, int DD, int S2, class FP, class FL>
-__global__ __launch_bounds__(kBlock) void k_gen_fused(GenFusedArgs a, FP fp, FL fl) {
-    const Tid t = Tid::here();
-    const int n = a.g.n;
-    long long ne = 0;
-    GridBarrier bar = a.bar;
-    int32_t *qin = a.q0, *qout = a.q1;
-    int it = 0, pulls = 0;
-    for (;;) {
-        if (it > 0 && load_relaxed(&a.cnt[8 + (it + 2) % 3]) != 0) break;
-        const int cnt = load_relaxed(&a.cnt[it % 3]);
-        if (cnt == 0) break;
-        if (t.block == 0 && threadIdx.x == 0) {
-            __hip_atomic_store(&a.cnt[(it + 2) % 3], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&a.cnt[8 + (it + 1) % 3], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        OutFrontier o{};
-        o.q = qout;
-        o.count = &a.cnt[(it + 1) % 3];
-        o.cap = a.cap;
-        o.overflow = &a.cnt[8 + it % 3];
-        const bool pull = S2 != 0 && (double)cnt > (double)a.threshold * (double)n;
-        if (!pull) {
-            if constexpr (DD == kDedupMonotonic) {
-                o.tags = a.tags;
-                o.iter = a.iter0 + it + 1;
-            }
-            const SrcQueue src{qin, cnt};
-            if constexpr (LB == GG_LB_VERTEX_BASED) lb_vp<kCreateFused, DD, false>(a.g, src, fp, o, t, ne);
-            else if constexpr (LB == GG_LB_WM) lb_wm<kCreateFused, DD>(a.g, src, fp, o, t, ne);
-            else if constexpr (LB == GG_LB_CM) lb_cm<kCreateFused, DD, false>(a.g, src, fp, o, t, ne);
-            else if constexpr (LB == GG_LB_STRICT) {
-                if (!grid_degree_scan(a.g, src, a.scan, a.scan_part, bar)) break;
-                lb_strict<kCreateFused, DD>(a.g, src, a.scan, fp, o, t, ne);
-            } else lb_etwc<kCreateFused, DD, false>(a.g, src, fp, o, t, ne);
-        } else {
-            pulls++;
-            // dense input map from the queue: clear, barrier, scatter, barrier
-            const long long stride = (long long)t.nblocks * kBlock;
-            const long long gid = (long long)t.block * kBlock + threadIdx.x;
-            if constexpr (S2 == 1) {
-                for (long long i = gid; i < n; i += stride) a.map_bool[i] = 0;
-            } else {
-                for (long long i = gid; i < (n + 63) / 64; i += stride) a.map_bits[i] = 0ull;
-            }
-            if (!grid_sync(bar)) break;
-            for (long long i = gid; i < cnt; i += stride) {
-                const int v = qin[i];
-                if constexpr (S2 == 1) a.map_bool[v] = 1;
-                else atomic_or_u64(&a.map_bits[v >> 6], 1ull << (v & 63));
-            }
-            if (!grid_sync(bar)) break;
-            if constexpr (S2 == 1) gen_pull_dev<kRepBoolmap, kCreateFused, false>(a.g, fl, a.map_bool, nullptr, o, t);
-            else if constexpr (S2 == 2) gen_pull_dev<kRepBitmap, kCreateFused, false>(a.g, fl, nullptr, a.map_bits, o, t);
-        }
-        if (!grid_sync(bar)) break;
-        int32_t *tq = qin;
-        qin = qout;
-        qout = tq;
-        it++;
+// The steps of a fused loop, for k_gen_fused and for the kernels generated
+// for fused loops with more statements than the operator: a round's head
+// (exit test, counters), its operator, whole-vertex applies, and its tail
+// (grid barrier, queue swap). Every lane of the grid runs every step.
+struct FusedLoopState {
+    Tid t;
+    GridBarrier bar;
+    int32_t *qin, *qout;
+    int it, pulls;
+};
+
+__device__ __forceinline__ FusedLoopState fused_begin(const GenFusedArgs &a) {
+    return FusedLoopState{Tid::here(), a.bar, a.q0, a.q1, 0, 0};
+}
+
+// The input frontier's size, or -1 when the loop ends: the frontier is empty,
+// or the previous round overflowed its queue. A round's overflow flag is read
+// at the head of the next round (after the barrier that ends the round that
+// raised it), so every workgroup leaves at the same round.
+__device__ __forceinline__ int fused_round_head(const GenFusedArgs &a, const FusedLoopState &s) {
+    const int it = s.it;
+    if (it > 0 && load_relaxed(&a.cnt[8 + (it + 2) % 3]) != 0) return -1;
+    const int cnt = load_relaxed(&a.cnt[it % 3]);
+    if (cnt == 0) return -1;
+    if (s.t.block == 0 && threadIdx.x == 0) {
+        __hip_atomic_store(&a.cnt[(it + 2) % 3], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.cnt[8 + (it + 1) % 3], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (t.block == 0 && threadIdx.x == 0) {
-        a.cnt[3] = it;
-        a.cnt[4] = pulls;
+    return cnt;
+}
+
+// LB: the PUSH load balancer; DD: kDedupNone or kDedupMonotonic; S2: 0 = PUSH
+// only, 1 / 2 = hybrid with a PULL step over a boolmap / bitmap. The round's
+// output goes to s.qout; false when a grid barrier was aborted.
+template <int LB, int DD, int S2, class FP, class FL>
+__device__ bool fused_step(const GenFusedArgs &a, FP &fp, FL &fl, FusedLoopState &s, int cnt) {
+    const int n = a.g.n;
+    const Tid t = s.t;
+    long long ne = 0;
+    OutFrontier o{};
+    o.q = s.qout;
+    o.count = &a.cnt[(s.it + 1) % 3];
+    o.cap = a.cap;
+    o.overflow = &a.cnt[8 + s.it % 3];
+    const bool pull = S2 != 0 && (double)cnt > (double)a.threshold * (double)n;
+    if (!pull) {
+        if constexpr (DD == kDedupMonotonic) {
+            o.tags = a.tags;
+            o.iter = a.iter0 + s.it + 1;
+        }
+        const SrcQueue src{s.qin, cnt};
+        if constexpr (LB == GG_LB_VERTEX_BASED) lb_vp<kCreateFused, DD, false>(a.g, src, fp, o, t, ne);
+        else if constexpr (LB == GG_LB_WM) lb_wm<kCreateFused, DD>(a.g, src, fp, o, t, ne);
+        else if constexpr (LB == GG_LB_CM) lb_cm<kCreateFused, DD, false>(a.g, src, fp, o, t, ne);
+        else if constexpr (LB == GG_LB_STRICT) {
+            if (!grid_degree_scan(a.g, src, a.scan, a.scan_part, s.bar)) return false;
+            lb_strict<kCreateFused, DD>(a.g, src, a.scan, fp, o, t, ne);
+        } else lb_etwc<kCreateFused, DD, false>(a.g, src, fp, o, t, ne);
+        return true;
+    }
+    s.pulls++;
+    // dense input map from the queue: clear, barrier, scatter, barrier
+    const long long stride = (long long)t.nblocks * kBlock;
+    const long long gid = (long long)t.block * kBlock + threadIdx.x;
+    if constexpr (S2 == 1) {
+        for (long long i = gid; i < n; i += stride) a.map_bool[i] = 0;
+    } else {
+        for (long long i = gid; i < (n + 63) / 64; i += stride) a.map_bits[i] = 0ull;
+    }
+    if (!grid_sync(s.bar)) return false;
+    for (long long i = gid; i < cnt; i += stride) {
+        const int v = s.qin[i];
+        if constexpr (S2 == 1) a.map_bool[v] = 1;
+        else atomic_or_u64(&a.map_bits[v >> 6], 1ull << (v & 63));
+    }
+    if (!grid_sync(s.bar)) return false;
+    if constexpr (S2 == 1) gen_pull_dev<kRepBoolmap, kCreateFused, false>(a.g, fl, a.map_bool, nullptr, o, t);
+    else if constexpr (S2 == 2) gen_pull_dev<kRepBitmap, kCreateFused, false>(a.g, fl, nullptr, a.map_bits, o, t);
+    return true;
+}
+
+// vertices.apply(f) inside a fused loop (the caller separates it from the
+// steps around it with grid barriers)
+template <class F>
+__device__ __forceinline__ void fused_vertices(int n, const F &f, Tid t) {
+    for (long long v = (long long)t.block * kBlock + threadIdx.x; v < n; v += (long long)t.nblocks * kBlock)
+        f((int)v);
+}
+
+// the barrier that ends a round, then the swap of the queues
+__device__ __forceinline__ bool fused_round_tail(FusedLoopState &s) {
+    if (!grid_sync(s.bar)) return false;
+    int32_t *tq = s.qin;
+    s.qin = s.qout;
+    s.qout = tq;
+    s.it++;
+    return true;
+}
+
+__device__ __forceinline__ void fused_end(const GenFusedArgs &a, const FusedLoopState &s) {
+    if (s.t.block == 0 && threadIdx.x == 0) {
+        a.cnt[3] = s.it;
+        a.cnt[4] = s.pulls;
     }
 }
 
-// Run `while (frontier not empty) frontier = step(frontier)` as one launch
-// from the live frontier of fs; advances iter by the rounds run and leaves fs
-// empty. Throws GG_ERR_OUT_OF_MEMORY when a round's output exceeded the
-// queue (deduplication disabled).
 template <int LB, int DD, int S2, class FP, class FL>
-void fused_loop(Ctx &c, Graph &G, const DevGraph &g, Workspace &ws, FrontierState &fs, float threshold, FP fp,
-                FL fl, int &iter) {
-    static_assert(LB == GG_LB_VERTEX_BASED || LB == GG_LB_WM || LB == GG_LB_CM || LB == GG_LB_STRICT ||
-                      LB == GG_LB_ETWC,
-                  "a fused loop runs VERTEX_BASED, WM, CM, STRICT or ETWC");
-    static_assert(DD == kDedupNone || DD == kDedupMonotonic, "a fused loop deduplicates with monotonic counters");
-    if (fs.count == 0) return;
+__global__ __launch_bounds__(kBlock) void k_gen_fused(GenFusedArgs a, FP fp, FL fl) {
+    FusedLoopState s = fused_begin(a);
+    for (;;) {
+        const int cnt = fused_round_head(a, s);
+        if (cnt < 0) break;
+        if (!fused_step<LB, DD, S2>(a, fp, fl, s, cnt)) break;
+        if (!fused_round_tail(s)) break;
+    }
+    fused_end(a, s);
+}
+
+// Host side of a fused loop over the live frontier of fs, for the persistent
+// kernel kern (which runs the loop): its grid, the loop state in device memory
+// (the first frontier's size, zeroed counters, barrier words, STRICT scan
+// buffers) and the arguments. The caller launches kern with
+// launch_cooperative(c, kern, blocks, ...) and then calls fused_complete.
+struct FusedLaunch {
+    GenFusedArgs a;
+    int blocks;
+};
+
+inline FusedLaunch fused_prepare(Ctx &c, Graph &G, const DevGraph &g, Workspace &ws, FrontierState &fs,
+                                 float threshold, const void *kern, bool strict, int iter) {
     const int32_t *q0 = fs.as_queue();
-    const void *kern = (const void *)k_gen_fused<LB, DD, S2, FP, FL>;
     const int blocks = fused_grid_for(kern, G, c.num_cus);
     const long long cap = fs.qcap < 0x7fffffffll ? fs.qcap : 0x7fffffffll;
-    if (LB == GG_LB_STRICT) {
+    if (strict) {
         ws.scan.ensure((size_t)cap + 1);
         ws.scan_part.ensure((size_t)blocks);
     }
@@ -328,15 +374,38 @@ void fused_loop(Ctx &c, Graph &G, const DevGraph &g, Workspace &ws, FrontierStat
                    prepare_barrier(c, ws, blocks),
                    ws.scan.p,
                    ws.scan_part.p};
-    void *args[] = {&a, &fp, &fl};
-    launch_cooperative(c, kern, blocks, args);
+    return FusedLaunch{a, blocks};
+}
+
+// After the launch: the barrier's abort flag, the overflow flags, the rounds
+// run (iter advances by them); leaves fs empty. Throws GG_ERR_OUT_OF_MEMORY
+// when a round's output exceeded the queue (deduplication disabled).
+inline void fused_complete(Ctx &c, Workspace &ws, FrontierState &fs, int &iter) {
     check_barrier(c, ws);
+    int32_t *cnt = ws.counters.p + 16;
     GG_HIP(hipMemcpyAsync(ws.h_i32.p, cnt, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
     GG_HIP(hipStreamSynchronize(c.s));
     require(ws.h_i32.p[8] == 0 && ws.h_i32.p[9] == 0 && ws.h_i32.p[10] == 0, GG_ERR_OUT_OF_MEMORY,
             "output frontier exceeded its queue capacity (enable deduplication)");
     iter += ws.h_i32.p[3];
     fs.count = 0;
+}
+
+// Run `while (frontier not empty) frontier = step(frontier)` as one launch
+// of k_gen_fused from the live frontier of fs.
+template <int LB, int DD, int S2, class FP, class FL>
+void fused_loop(Ctx &c, Graph &G, const DevGraph &g, Workspace &ws, FrontierState &fs, float threshold, FP fp,
+                FL fl, int &iter) {
+    static_assert(LB == GG_LB_VERTEX_BASED || LB == GG_LB_WM || LB == GG_LB_CM || LB == GG_LB_STRICT ||
+                      LB == GG_LB_ETWC,
+                  "a fused loop runs VERTEX_BASED, WM, CM, STRICT or ETWC");
+    static_assert(DD == kDedupNone || DD == kDedupMonotonic, "a fused loop deduplicates with monotonic counters");
+    if (fs.count == 0) return;
+    const void *kern = (const void *)k_gen_fused<LB, DD, S2, FP, FL>;
+    FusedLaunch L = fused_prepare(c, G, g, ws, fs, threshold, kern, LB == GG_LB_STRICT, iter);
+    void *args[] = {&L.a, &fp, &fl};
+    launch_cooperative(c, kern, L.blocks, args);
+    fused_complete(c, ws, fs, iter);
 }
 
 }  // namespace gen

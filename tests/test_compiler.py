@@ -135,12 +135,38 @@ def test_kernel_fusion_refusals(cfg, match):
         compile_source(src, ["parent"])
 
 
-def test_fused_loop_body_must_be_the_operator():
+def test_fused_loop_statements():
+    # a vector element written from the host cannot run inside the fused loop
     src = variant_source("bfs_fused_hybrid_strict").replace(
         "        delete frontier;\n        frontier = output;\n    end",
         "        delete frontier;\n        frontier = output;\n        parent[0] = 0;\n    end")
-    with pytest.raises(CompileError, match="fused loop holds"):
+    with pytest.raises(CompileError, match="cannot run inside a fused loop"):
         compile_source(src, ["parent"])
+    # nor a scalar statement that reads vertex data
+    src = variant_source("bfs_rounds_fused").replace("rounds = rounds + 1;", "rounds = parent[0];")
+    with pytest.raises(CompileError, match="local variables and literals"):
+        compile_source(src, ["parent"])
+
+
+def test_fused_loop_hoisting():
+    code, notes = gen("bfs_rounds_fused")
+    # one generated persistent kernel with the loop, main's locals hoisted in and out
+    assert "__global__ __launch_bounds__(kBlock) void k_fused_0(gen::GenFusedArgs a," in code
+    assert "int64_t h_rounds = hoist[0];" in code and "hoist[1] = h_work;" in code
+    assert "gen::fused_vertices(a.g.n, vf0, s.t);" in code
+    assert "gen::fused_step<GG_LB_STRICT, kDedupMonotonic, 2>(a, fp, fl, s, cnt)" in code
+    k = code.index("void k_fused_0")
+    body = code[k:code.index("\n}\n", k)]
+    # statement order of the loop body: counter, vertex apply + barrier, operator, recurrence, tail
+    order = [body.index(x) for x in ("h_rounds = (h_rounds + 1);", "gen::fused_vertices", "grid_sync(s.bar)",
+                                     "gen::fused_step", "h_work = ((h_work + (2 * h_rounds)) - 1);",
+                                     "gen::fused_round_tail")]
+    assert order == sorted(order)
+    assert any("hoisted to device memory: rounds, work" in n for n in notes)
+    # the unfused form runs the same statements on the host around the operator
+    code, _ = gen("bfs_rounds")
+    assert "h_rounds += 0" not in code and "h_rounds = (h_rounds + 1);" in code
+    assert "while (fs.count > 0)" in code and "k_fused_" not in code
 
 
 def test_edge_blocking_refused():

@@ -137,3 +137,19 @@ def test_generated_errors():
     assert e.value.status == gg.ERR_INVALID_ARG
     # the module still runs after the errors
     check_parents(h, m.run(G, [3])["parent"].cpu().numpy(), 3)
+
+
+@pytest.mark.parametrize("variant", ["bfs_rounds", "bfs_rounds_fused"])
+@pytest.mark.parametrize("name", SYM + ["drmat12"])
+def test_generated_loop_statements(variant, name):
+    """Scalar statements and a vertex operator inside the frontier loop: run on
+    the host around each round, or inside the one persistent kernel with main's
+    locals hoisted to device memory; both give the same counts."""
+    g, s = host(name), src_of(name)
+    out = module(variant).run(dev(name), [s])
+    parent = out["parent"].cpu().numpy()
+    check_parents(g, parent, s)
+    rounds = int(oracle.bfs(g.n, g.row_ptr, g.col, s).max()) + 1  # non-empty frontiers
+    info = out["info"].cpu().numpy()
+    assert info[0] == rounds and info[1] == 10 + rounds * rounds  # work += 2 * round - 1 each round
+    assert (out["seen"].cpu().numpy() == rounds).all()
