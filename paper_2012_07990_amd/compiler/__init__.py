@@ -225,6 +225,24 @@ VARIANTS = {
     s2.configDirection(PULL, BITMAP);
     HybridGPUSchedule h1(INPUT_VERTEXSET_SIZE, 0.05, s1, s2);
     program->applyGPUSchedule("s1", h1);"""),
+    "sssp_pq_strict_d64": ("sssp_pq.gt", ["dist"], None),
+    "sssp_pq_etwc_d1": ("sssp_pq.gt", ["dist"], """
+    SimpleGPUSchedule s1;
+    s1.configLoadBalance(ETWC);
+    s1.configDelta(1);
+    program->applyGPUSchedule("s1", s1);"""),
+    "sssp_pq_cm_d4096_boolmap": ("sssp_pq.gt", ["dist"], """
+    SimpleGPUSchedule s1;
+    s1.configLoadBalance(CM);
+    s1.configDelta(4096);
+    s1.configFrontierCreation(UNFUSED_BOOLMAP);
+    program->applyGPUSchedule("s1", s1);"""),
+    "sssp_pq_vp_d512_nodedup": ("sssp_pq.gt", ["dist"], """
+    SimpleGPUSchedule s1;
+    s1.configLoadBalance(VERTEX_BASED);
+    s1.configDelta(512);
+    s1.configDeduplication(DISABLED);
+    program->applyGPUSchedule("s1", s1);"""),
     "pagerank_pull": ("pagerank.gt", ["old_rank"], None),
     "pagerank_push_strict": ("pagerank.gt", ["old_rank"], """
     SimpleGPUSchedule s1;

@@ -123,8 +123,11 @@ class ExprGen:
     """C++ text of an expression in a function of the program; `names` maps
     the function's vertex parameters to C++ variables."""
 
-    def __init__(self, prog: Program, names: Dict[str, str], weight: Optional[str] = None, host=False):
-        self.prog, self.names, self.weight, self.host = prog, names, weight, host
+    def __init__(self, prog: Program, names: Dict[str, str], weight: Optional[str] = None, host=False,
+                 wide=False):
+        # wide: integer vector elements and weights are read as int64_t, so
+        # sums of a priority and a weight cannot wrap
+        self.prog, self.names, self.weight, self.host, self.wide = prog, names, weight, host, wide
 
     def __call__(self, e) -> str:
         k = e[0]
@@ -138,7 +141,7 @@ class ExprGen:
             if n in self.names:
                 return self.names[n]
             if self.weight is not None and n == self.weight:
-                return "(int32_t)w[e]"
+                return "(int64_t)w[e]" if self.wide else "(int32_t)w[e]"
             if n in self.prog.scalars:
                 return "s_" + n
             raise CompileError("unknown name %r" % n)
@@ -148,6 +151,8 @@ class ExprGen:
                 raise CompileError("only vectors are indexed")
             if self.host:
                 raise CompileError("main reads vector elements only through operators")
+            if self.wide and self.prog.vectors[base[1]]["type"] in ("int", "bool"):
+                return "(int64_t)vec_%s[%s]" % (base[1], self(e[2]))
             return "vec_%s[%s]" % (base[1], self(e[2]))
         if k == "bin":
             return "(%s %s %s)" % (self(e[2]), e[1], self(e[3]))
@@ -301,6 +306,58 @@ def edge_functor(prog: Program, f: Func, direction: str, filt: Optional[Func], t
 """ % (cname, members, fcond, fcond, body, ret)
 
 
+def pq_edge_functor(prog: Program, f: Func, pq: str, cname: str, notes: List[str]) -> str:
+    """Functor for edges.from(frontier).applyUpdatePriority(f): f's local
+    variables, then pq.updatePriorityMin(dst, value) lowered to an atomic
+    minimum on the priority vector that also sorts the destination into the
+    ready set (current bucket) or the far queue (a later bucket)."""
+    if len(f.params) not in (2, 3):
+        raise CompileError("edge function %s takes (src, dst[, weight])" % f.name)
+    src, dst = f.params[0][0], f.params[1][0]
+    weight = f.params[2][0] if len(f.params) == 3 else None
+    names = {src: "u", dst: "v"}
+    members = "".join("    %s *vec_%s;\n" % (CTYPE[prog.vectors[v]["type"]], v) for v in sorted(prog.vectors))
+    members += "".join("    double s_%s;\n" % s for s in sorted(prog.scalars))
+    members += "    const uint32_t *w;\n    gen::PQView pq;\n"
+    lines, ups = [], []
+    for st in f.body:
+        if st[0] == "var" and st[2][0] == "scalar" and st[3] is not None:
+            lname = "l_" + st[1]
+            lines.append("const int64_t %s = (int64_t)(%s);" % (lname, ExprGen(prog, names, weight, wide=True)(st[3])))
+            names[st[1]] = lname
+        elif (st[0] == "expr" and st[1][0] == "method" and st[1][1] == ("id", pq)
+              and st[1][2] == "updatePriorityMin"):
+            args = st[1][3]
+            if len(args) != 2 or args[0] != ("id", dst):
+                raise CompileError("%s.updatePriorityMin(%s, value) updates the destination" % (pq, dst))
+            k = len(ups)
+            lines.append("bool tf_%d; const bool n_%d = gen::pq_update_min(pq, v, (long long)(%s), tf_%d);"
+                         % (k, k, ExprGen(prog, names, weight, wide=True)(args[1]), k))
+            lines.append("wave_append(pq.farq, pq.farc, pq.far_cap, pq.flags + 1, tf_%d, v);" % k)
+            ups.append("n_%d" % k)
+        else:
+            raise CompileError("edge function %s: local variables and %s.updatePriorityMin(...) are supported "
+                               "under applyUpdatePriority" % (f.name, pq))
+    if not ups:
+        raise CompileError("edge function %s does not call %s.updatePriorityMin" % (f.name, pq))
+    notes.append("%s: %s.updatePriorityMin -> atomic minimum on the priority vector, bucket test, ready set "
+                 "or far queue (PUSH)" % (f.name, pq))
+    return """struct %s {
+%s    __device__ __forceinline__ bool active(int) const { return true; }
+    __device__ __forceinline__ bool done(int) const { return false; }
+    using Pre = int;
+    __device__ __forceinline__ Pre load(int, int, int) const { return 0; }
+    __device__ __forceinline__ int apply(int u, int v, int e, Pre) const {
+        %s
+        return (%s) ? v : -1;
+    }
+    __device__ __forceinline__ int edge(int u, int v, int e) const { return apply(u, v, e, 0); }
+    __device__ __forceinline__ void begin() const {}
+    __device__ __forceinline__ void flush() const {}
+};
+""" % (cname, members, "\n        ".join(lines), " || ".join(ups))
+
+
 def vertex_functor(prog: Program, f: Func, cname: str) -> str:
     if len(f.params) != 1:
         raise CompileError("vertex function %s takes (v)" % f.name)
@@ -335,6 +392,7 @@ class MainGen:
         self.prog, self.scheds, self.notes = prog, scheds, notes
         self.functors: Dict[str, str] = {}   # C++ name -> definition
         self.fused_kernels: List[str] = []   # persistent kernels of fused loops
+        self.pq_made: Dict[str, bool] = {}     # priority queues created in main
         self.host_vars: Dict[str, str] = {}
         self.frontiers: Dict[str, str] = {}  # program name -> "fs"
         self.labels_used: List[str] = []
@@ -427,7 +485,9 @@ class MainGen:
                         if self.frontiers:
                             raise CompileError("line %d: one frontier variable per program is supported" % line)
                         self.frontiers[name] = "fs"
-                        arg = init[2]
+                        if len(init[2]) != 1:
+                            raise CompileError("line %d: new vertexset{Vertex}(size) takes one argument" % line)
+                        arg = init[2][0]
                         if arg == ("num", "0"):
                             self.emit("fs.count = 0;", depth)
                         elif arg[0] == "method" and arg[2] == "size" and arg[1] == ("id", self.prog.vertices):
@@ -444,7 +504,9 @@ class MainGen:
                     raise CompileError("line %d: unsupported variable type %r" % (line, ty))
             elif k == "assign":
                 _, op, lhs, rhs, label, line = st
-                if lhs[0] == "id" and lhs[1] in self.host_vars and op in ("=", "+="):
+                if lhs[0] == "id" and lhs[1] in self.prog.pqs:
+                    self.pq_create(lhs[1], rhs, line, depth)
+                elif lhs[0] == "id" and lhs[1] in self.host_vars and op in ("=", "+="):
                     self.emit("%s %s %s;" % (self.host_vars[lhs[1]], op, self.hexpr(rhs)), depth)
                 elif lhs[0] == "index" and lhs[1][0] == "id" and lhs[1][1] in self.prog.vectors and op == "=":
                     vec = lhs[1][1]
@@ -456,6 +518,8 @@ class MainGen:
             elif k == "expr":
                 _, e, label, line = st
                 self.call(e, label, line, depth)
+            elif k == "while" and self.pq_cond(st[1]) is not None:
+                self.pq_loop(self.pq_cond(st[1]), st[2], st[4], depth)
             elif k == "while":
                 _, cond, wbody, label, line = st
                 if not (cond[0] == "bin" and cond[1] == "!=" and cond[3] == ("num", "0") and cond[2][0] == "method"
@@ -487,6 +551,77 @@ class MainGen:
             else:
                 raise CompileError("unsupported statement %r" % (k,))
             i += 1
+
+    def pq_create(self, pq, rhs, line, depth):
+        """pq = new priority_queue{Vertex}(int)(priority_vector, start_vertex)"""
+        if rhs[0] != "new" or rhs[1][0] != "pq" or len(rhs[2]) != 2 or rhs[2][0][0] != "id" \
+                or rhs[2][0][1] not in self.prog.vectors:
+            raise CompileError("line %d: %s = new priority_queue{Vertex}(int)(vector, start_vertex)" % (line, pq))
+        vec = rhs[2][0][1]
+        if self.prog.vectors[vec]["type"] != "int":
+            raise CompileError("line %d: the priority vector %s must hold int" % (line, vec))
+        if pq in self.pq_made:
+            raise CompileError("line %d: %s is created once" % (line, pq))
+        self.pq_made[pq] = True
+        self.emit("gen::PQState pq_%s;" % pq, depth)
+        self.emit("pq_%s.prio = vec_%s.p;" % (pq, vec), depth)
+        self.emit("pq_%s.start = (int64_t)(%s);" % (pq, self.hexpr(rhs[2][1])), depth)
+        self.emit("pq_%s.n = g.n;" % pq, depth)
+
+    def pq_cond(self, cond):
+        """The queue of `while (pq.finished() == false)` (or `!pq.finished()`), else None."""
+        def fin(e):
+            return e[0] == "method" and e[2] == "finished" and e[1][0] == "id" and e[1][1] in self.prog.pqs
+        if cond[0] == "bin" and cond[1] == "==" and fin(cond[2]) and cond[3] == ("bool", False):
+            return cond[2][1][1]
+        if cond[0] == "un" and cond[1] == "!" and fin(cond[2]):
+            return cond[2][1][1]
+        return None
+
+    def pq_loop(self, pq, body, line, depth):
+        """while (pq.finished() == false): frontier = pq.dequeue_ready_set();
+        edges.from(frontier).applyUpdatePriority(f); delete frontier;"""
+        if pq not in self.pq_made:
+            raise CompileError("line %d: %s is used before it is created" % (line, pq))
+        ok = (len(body) == 3 and body[0][0] == "var" and body[0][2] == ("vertexset",)
+              and body[0][3] is not None and body[0][3][0] == "method" and body[0][3][2] == "dequeue_ready_set"
+              and body[0][3][1] == ("id", pq) and body[1][0] == "expr" and body[2][0] == "delete"
+              and body[2][1] == body[0][1])
+        if not ok:
+            raise CompileError("line %d: the loop of %s holds `var f : vertexset{..} = %s.dequeue_ready_set();`, "
+                               "`edges.from(f).applyUpdatePriority(update);` and `delete f;`" % (line, pq, pq))
+        fname = body[0][1]
+        e, label = body[1][1], body[1][2]
+        if not (e[0] == "method" and e[2] == "applyUpdatePriority" and len(e[3]) == 1 and e[3][0][0] == "id"
+                and e[1][0] == "method" and e[1][2] == "from" and e[1][1] == ("id", self.prog.edges["name"])
+                and e[1][3] == [("id", fname)]):
+            raise CompileError("line %d: expected %s.from(%s).applyUpdatePriority(update)"
+                               % (body[1][-1], self.prog.edges["name"], fname))
+        if self.frontiers and fname not in self.frontiers:
+            raise CompileError("line %d: one frontier variable per program is supported" % line)
+        self.frontiers[fname] = "fs"
+        udf = self.prog.funcs.get(e[3][0][1])
+        if udf is None:
+            raise CompileError("unknown function %s" % e[3][0][1])
+        if len(udf.params) == 3 and not self.prog.edges["weighted"]:
+            raise CompileError("%s takes a weight but the edgeset is unweighted" % udf.name)
+        s = self.scheds.get(label) if label else None
+        for x in ([s["s1"], s["s2"]] if s and s["hybrid"] else [s["s1"]] if s else []):
+            if x["direction"] != "GG_PUSH" or x["kernel_fusion"]:
+                raise CompileError("line %d: applyUpdatePriority runs unfused PUSH steps" % line)
+        delta = s["s1"]["delta"] if s else 1
+        sname = self.sched(label)
+        cname = "P_%s_%s" % (udf.name, pq)
+        if cname not in self.functors:
+            self.functors[cname] = pq_edge_functor(self.prog, udf, pq, cname, self.notes)
+        init = self.init_list(True)[:-1] + ", gen::pq_view(pq_%s)}" % pq
+        self.emit("gen::pq_start(c, *ws, fs, pq_%s, %d);" % (pq, delta), depth)
+        self.emit("while (gen::pq_next(c, *ws, fs, pq_%s, iter)) {" % pq, depth)
+        self.emit("    const gg_simple_schedule &sc = pick(%s, fs.count, g.n);" % sname, depth)
+        self.emit("    gen::frontier_step(c, g, *ws, fs, sc, %s%s, ++iter);" % (cname, init), depth)
+        self.emit("}", depth)
+        self.notes.append("priority queue %s: buckets of width %d (configDelta), ready set in the frontier, "
+                          "later buckets in a far queue" % (pq, delta))
 
     def dexpr(self, e) -> str:
         """A scalar expression inside a fused loop: hoisted locals of main and literals."""

@@ -60,6 +60,7 @@ class Program:
     vectors: Dict[str, dict] = field(default_factory=dict)   # name -> {"type", "init"}
     scalars: Dict[str, dict] = field(default_factory=dict)   # name -> {"type", "init"}
     funcs: Dict[str, Func] = field(default_factory=dict)
+    pqs: Dict[str, dict] = field(default_factory=dict)   # priority queues: name -> {"type"}
     schedule: list = field(default_factory=list)     # scheduling statements (tuples)
 
 
@@ -114,7 +115,11 @@ class Parser:
             self.expect(")")
             return ("vector", elem)
         if name == "priority_queue":
-            raise CompileError("priority queues are not part of the supported subset (use min= with a frontier loop)")
+            self.expect("{"); self.ident(); self.expect("}")
+            self.expect("(")
+            elem = self.ident()
+            self.expect(")")
+            return ("pq", elem)
         return ("scalar", name)
 
     # -- expressions ------------------------------------------------------------------
@@ -149,10 +154,7 @@ class Parser:
             return e
         if t[1] == "new":
             ty = self.type_()
-            self.expect("(")
-            arg = self.expr()
-            self.expect(")")
-            return ("new", ty, arg)
+            return ("new", ty, self.args())
         if t[0] == "id":
             if t[1] in ("true", "false"):
                 return ("bool", t[1] == "true")
@@ -256,10 +258,18 @@ class Parser:
                 name = self.ident()
                 self.expect(":")
                 ty = self.type_()
-                self.expect("=")
-                init = self.expr()
+                init = None
+                if ty[0] == "pq":
+                    if self.at("="):
+                        raise CompileError("line %d: a priority queue is created in main "
+                                           "(pq = new priority_queue{Vertex}(int)(vector, start))" % self.peek()[2])
+                else:
+                    self.expect("=")
+                    init = self.expr()
                 self.expect(";")
-                if ty[0] == "edgeset":
+                if ty[0] == "pq":
+                    p.pqs[name] = {"type": ty[1]}
+                elif ty[0] == "edgeset":
                     p.edges = {"name": name, "weighted": ty[1]}
                 elif ty[0] == "vertexset":
                     p.vertices = name

@@ -19,6 +19,8 @@
 // are separated by the grid barrier of fused.hpp.
 #pragma once
 
+#include <climits>
+
 #include "algos.hpp"
 #include "driver.hpp"
 #include "fused.hpp"
@@ -406,6 +408,164 @@ void fused_loop(Ctx &c, Graph &G, const DevGraph &g, Workspace &ws, FrontierStat
     void *args[] = {&L.a, &fp, &fl};
     launch_cooperative(c, kern, L.blocks, args);
     fused_complete(c, ws, fs, iter);
+}
+
+
+// ---- priority queue: applyUpdatePriority with configDelta ----------------------
+// Buckets of width delta over an int32 priority vector (the delta-stepping
+// priority queue that configDelta parameterises). The ready set is the live
+// frontier of fs: vertices of the current bucket k whose priority dropped.
+// Later buckets wait in a far queue (a vertex enters each far queue
+// generation at most once, by a tag); when the ready set runs empty, the
+// smallest bucket in the far queue becomes current and its entries move to
+// the ready set.
+struct PQView {  // what a generated update functor needs on the device
+    int32_t *prio;
+    long long bucket_end;  // (k + 1) * delta
+    int32_t *farq, *farc;  // the far queue being filled and its size
+    int32_t far_cap;
+    int32_t *far_tag;
+    int32_t far_id;
+    int32_t *flags;        // [0] a priority past INT32_MAX - 1, [1] far queue overflow
+};
+
+// updatePriorityMin(v, nd): lower prio[v] to nd; true when v joins the ready
+// set (its new priority is in the current bucket); to_far when it joins the
+// far queue. The caller appends to_far lanes with wave_append (every lane that
+// runs the update takes part).
+__device__ __forceinline__ bool pq_update_min(const PQView &q, int v, long long nd, bool &to_far) {
+    to_far = false;
+    if (nd > (long long)INT_MAX - 1) {
+        q.flags[0] = 1;
+        return false;
+    }
+    if (nd >= q.prio[v]) return false;  // a stale, larger read only costs the atomic
+    const int old = atomic_min_i32(&q.prio[v], (int)nd);
+    if (nd >= old) return false;
+    if (nd < q.bucket_end) return true;
+    to_far = q.far_tag[v] < q.far_id && atomic_max_i32(&q.far_tag[v], q.far_id) < q.far_id;
+    return false;
+}
+
+// smallest bucket beyond k among the far entries (one atomic per workgroup,
+// read first)
+__global__ __launch_bounds__(kBlock) inline void k_pq_far_min(const int32_t *farq, const int32_t *fc,
+                                                               const int32_t *prio, int delta, int k, int32_t *kmin) {
+    __shared__ int s_m[kBlock / kWave];
+    const int n = *fc;
+    int local = INT_MAX;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const int b = prio[farq[i]] / delta;
+        if (b > k && b < local) local = b;
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const int o = __shfl_xor(local, off, kWave);
+        local = o < local ? o : local;
+    }
+    if (lane_id() == 0) s_m[threadIdx.x / kWave] = local;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int m = INT_MAX;
+        for (int w = 0; w < kBlock / kWave; w++) m = s_m[w] < m ? s_m[w] : m;
+        if (m != INT_MAX && m < load_relaxed(kmin)) atomic_min_i32(kmin, m);
+    }
+}
+
+// far entries of bucket knew -> the ready set (deduplicated by the tags of
+// `near`); entries of later buckets -> the next far queue generation
+__global__ __launch_bounds__(kBlock) inline void k_pq_far_split(const int32_t *farq, const int32_t *fc,
+                                                                 const int32_t *prio, int delta, int knew,
+                                                                 OutFrontier near, int32_t *nfarq, int32_t *nfarc,
+                                                                 int far_cap, int32_t *far_tag, int far_id,
+                                                                 int32_t *flags) {
+    const int n = *fc;
+    const int stride = gridDim.x * kBlock;
+    const int iters = (n + stride - 1) / stride;
+    for (int it = 0; it < iters; it++) {  // wave-uniform trip count for the appends
+        const int i = it * stride + blockIdx.x * kBlock + threadIdx.x;
+        bool to_near = false, to_far = false;
+        int v = 0;
+        if (i < n) {
+            v = farq[i];
+            const int b = prio[v] / delta;
+            if (b == knew) to_near = dedup_first<kDedupMonotonic>(near, v);
+            else if (b > knew) to_far = far_tag[v] < far_id && atomic_max_i32(&far_tag[v], far_id) < far_id;
+        }
+        wave_append(near.q, near.count, near.cap, near.overflow, to_near, v);
+        wave_append(nfarq, nfarc, far_cap, flags + 1, to_far, v);
+    }
+}
+
+struct PQState {
+    int32_t *prio = nullptr;
+    int64_t start = -1;
+    int n = 0;
+    int delta = 1;
+    int k = 0;   // current bucket
+    int fe = 0;  // far queue generation being filled
+    int32_t *farq[2] = {nullptr, nullptr};
+    int32_t *ctr = nullptr;  // [0..1] far sizes, [2] bucket minimum, [4..5] flags
+    int32_t *tags = nullptr;
+};
+
+// `pq = new priority_queue(prio, start)` then the loop's first round: the
+// ready set holds start, the current bucket is prio[start] / delta
+inline void pq_start(Ctx &c, Workspace &ws, FrontierState &fs, PQState &pq, int delta) {
+    require(pq.prio != nullptr, GG_ERR_INVALID_ARG, "the priority queue was not created");
+    require(pq.start >= 0 && pq.start < pq.n, GG_ERR_INVALID_ARG, "vertex index out of range");
+    require(delta >= 1, GG_ERR_INVALID_ARG, "delta must be >= 1");
+    pq.delta = delta;
+    for (int i = 0; i < 3; i++) ws.aux_i32[i].ensure((size_t)pq.n);
+    pq.farq[0] = ws.aux_i32[0].p;
+    pq.farq[1] = ws.aux_i32[1].p;
+    pq.tags = ws.aux_i32[2].p;
+    fill_i32(c, pq.tags, pq.n, 0);
+    pq.ctr = ws.counters.p + 40;
+    fill_i32(c, pq.ctr, 8, 0);
+    const int p0 = read_i32(c, pq.prio + pq.start, ws.h_i32.p);
+    require(p0 != INT_MAX, GG_ERR_INVALID_ARG, "the start vertex has no priority");
+    pq.k = p0 / delta;
+    pq.fe = 0;
+    fs.count = 0;
+    add_vertex(c, fs, pq.n, pq.start);
+}
+
+inline PQView pq_view(const PQState &pq) {
+    return PQView{pq.prio, (long long)(pq.k + 1) * pq.delta, pq.farq[pq.fe & 1], pq.ctr + (pq.fe & 1), pq.n,
+                  pq.tags, pq.fe + 1, pq.ctr + 4};
+}
+
+// `while (pq.finished() == false)` with `frontier = pq.dequeue_ready_set()`:
+// true while a ready set is left (fs holds it); an empty ready set advances
+// to the smallest bucket in the far queue
+inline bool pq_next(Ctx &c, Workspace &ws, FrontierState &fs, PQState &pq, int &iter) {
+    for (;;) {
+        if (fs.count > 0) return true;
+        GG_HIP(hipMemcpyAsync(ws.h_i32.p, pq.ctr, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
+        GG_HIP(hipStreamSynchronize(c.s));
+        require(ws.h_i32.p[4] == 0, GG_ERR_OVERFLOW, "a priority exceeds INT32_MAX-1");
+        require(ws.h_i32.p[5] == 0, GG_ERR_OUT_OF_MEMORY, "far queue overflow");
+        const int fc = ws.h_i32.p[pq.fe & 1];
+        if (fc == 0) return false;
+        fill_i32(c, pq.ctr + 2, 1, INT_MAX);
+        hipLaunchKernelGGL(k_pq_far_min, dim3(blocks_for(fc, kBlock * 4, 1024)), dim3(kBlock), 0, c.s,
+                           pq.farq[pq.fe & 1], pq.ctr + (pq.fe & 1), pq.prio, pq.delta, pq.k, pq.ctr + 2);
+        GG_CHECK_LAUNCH();
+        const int knew = read_i32(c, pq.ctr + 2, ws.h_i32.p + 8);
+        if (knew == INT_MAX) return false;
+        fill_i32(c, pq.ctr + ((pq.fe + 1) & 1), 1, 0);
+        OutFrontier o = fs.prep_out(kCreateFused, kDedupMonotonic, iter++);
+        hipLaunchKernelGGL(k_pq_far_split, dim3(blocks_for(fc, kBlock, 1024)), dim3(kBlock), 0, c.s,
+                           pq.farq[pq.fe & 1], pq.ctr + (pq.fe & 1), pq.prio, pq.delta, knew, o,
+                           pq.farq[(pq.fe + 1) & 1], pq.ctr + ((pq.fe + 1) & 1), pq.n, pq.tags, pq.fe + 2,
+                           pq.ctr + 4);
+        GG_CHECK_LAUNCH();
+        c.launches += 2;
+        fs.commit(kCreateFused);
+        pq.fe++;
+        pq.k = knew;
+    }
 }
 
 }  // namespace gen

@@ -176,6 +176,35 @@ def test_edge_blocking_refused():
         compile_source(src, ["IDs"])
 
 
+PQ = open(os.path.join(compiler.EXAMPLES, "sssp_pq.gt")).read()
+
+
+def test_priority_queue_lowering():
+    code, notes = gen("sssp_pq_strict_d64")
+    f = functor(code, "P_relax_pq")
+    # the candidate is summed in 64 bits; the update is the queue's atomic-minimum bucket test
+    assert "const int64_t l_candidate = (int64_t)(((int64_t)vec_dist[u] + (int64_t)w[e]));" in f
+    assert "gen::pq_update_min(pq, v, (long long)(l_candidate), tf_0)" in f
+    assert "wave_append(pq.farq, pq.farc, pq.far_cap, pq.flags + 1, tf_0, v);" in f
+    assert "gen::pq_start(c, *ws, fs, pq_pq, 64);" in code
+    assert "while (gen::pq_next(c, *ws, fs, pq_pq, iter))" in code
+    assert any("buckets of width 64 (configDelta)" in n for n in notes)
+    assert "gen::pq_start(c, *ws, fs, pq_pq, 1);" in gen("sssp_pq_etwc_d1")[0]
+    assert "gen::pq_start(c, *ws, fs, pq_pq, 4096);" in gen("sssp_pq_cm_d4096_boolmap")[0]
+
+
+@pytest.mark.parametrize("edit,match", [
+    (("s1.configDelta(64);", "s1.configDelta(64);\n    s1.configDirection(PULL);"), "unfused PUSH"),
+    (("s1.configDelta(64);", "s1.configDelta(64);\n    s1.configKernelFusion(ENABLED);"), "unfused PUSH"),
+    (("pq = new priority_queue{Vertex}(int)(dist, start_vertex);\n", ""), "before it is created"),
+    (("        delete frontier;\n    end", "    end"), "loop of pq holds"),
+    (("pq.updatePriorityMin(dst, candidate);", "dist[dst] min= candidate;"), "updatePriorityMin"),
+])
+def test_priority_queue_refusals(edit, match):
+    with pytest.raises(CompileError, match=match):
+        compile_source(PQ.replace(*edit), ["dist"])
+
+
 def test_host_writes_are_checked():
     code, _ = gen("bfs_push_twce")
     assert "gen::set_one<int32_t>(c, vec_parent.p, g.n, (int64_t)(h_start_vertex)" in code
@@ -201,7 +230,7 @@ def _with_main(body):
     (BFS.replace("func main()", "func notmain()"), "no main"),
     (BFS.replace("const parent : vector{Vertex}(int) = -1;",
                  "const parent : vector{Vertex}(int) = -1;\nconst pq : priority_queue{Vertex}(int) = 0;"),
-     "priority queues"),
+     "created in main"),
     (_with_main("""
     var frontier : vertexset{Vertex} = new vertexset{Vertex}(0);
     frontier.addVertex(0);

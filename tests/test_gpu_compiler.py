@@ -92,6 +92,18 @@ def test_generated_sssp(variant, name):
     assert np.array_equal(dist, oracle.sssp(g.n, g.row_ptr, g.col, g.w, s))
 
 
+PQ_VARIANTS = ["sssp_pq_strict_d64", "sssp_pq_etwc_d1", "sssp_pq_cm_d4096_boolmap", "sssp_pq_vp_d512_nodedup"]
+
+
+@pytest.mark.parametrize("variant", PQ_VARIANTS)
+@pytest.mark.parametrize("name", SYM + ["drmat12"])
+def test_generated_priority_queue(variant, name):
+    """applyUpdatePriority over the delta-stepping buckets configDelta sets."""
+    g, s = host(name), src_of(name)
+    dist = module(variant).run(dev(name), [s])["dist"].cpu().numpy()
+    assert np.array_equal(dist, oracle.sssp(g.n, g.row_ptr, g.col, g.w, s))
+
+
 @pytest.mark.parametrize("variant", ["sssp_push_strict", "sssp_push_vp_nodedup", "sssp_fused_etwc"])
 def test_generated_sssp_directed(variant):
     g, s = host("drmat12"), src_of("drmat12")
