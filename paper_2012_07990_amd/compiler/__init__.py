@@ -244,6 +244,11 @@ VARIANTS = {
     s1.configDeduplication(DISABLED);
     program->applyGPUSchedule("s1", s1);"""),
     "pagerank_pull": ("pagerank.gt", ["old_rank"], None),
+    "pagerank_push_blocked": ("pagerank.gt", ["old_rank"], """
+    SimpleGPUSchedule s1;
+    s1.configDirection(PUSH);
+    s1.configLoadBalance(EDGE_ONLY, BLOCKED, 1000);
+    program->applyGPUSchedule("s1", s1);"""),
     "pagerank_push_strict": ("pagerank.gt", ["old_rank"], """
     SimpleGPUSchedule s1;
     s1.configDirection(PUSH);

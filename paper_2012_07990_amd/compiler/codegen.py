@@ -79,8 +79,11 @@ def lower_schedules(prog: Program) -> Dict[str, dict]:
                     raise CompileError("unknown load balance %r" % vals[0])
                 s["load_balance"] = LB[vals[0]]
                 if vals[0] == "EDGE_ONLY" and len(vals) > 1 and vals[1] == "BLOCKED":
-                    raise CompileError("EdgeBlocking is not generated for compiled programs (the library's "
-                                       "PageRank runs it)")
+                    s["edge_blocking"] = 1
+                    if len(vals) > 2:
+                        s["blocking_size"] = int(vals[2])
+                        if s["blocking_size"] < 1:
+                            raise CompileError("blocking size must be >= 1")
             elif method == "configFrontierCreation":
                 s["frontier_creation"] = CREATE[vals[0]]
             elif method == "configDeduplication":
@@ -552,6 +555,10 @@ class MainGen:
                 raise CompileError("unsupported statement %r" % (k,))
             i += 1
 
+    def blocked(self, label) -> bool:
+        s = self.scheds.get(label) if label else None
+        return bool(s) and any(x["edge_blocking"] for x in ([s["s1"], s["s2"]] if s["hybrid"] else [s["s1"]]))
+
     def pq_create(self, pq, rhs, line, depth):
         """pq = new priority_queue{Vertex}(int)(priority_vector, start_vertex)"""
         if rhs[0] != "new" or rhs[1][0] != "pq" or len(rhs[2]) != 2 or rhs[2][0][0] != "id" \
@@ -769,6 +776,9 @@ class MainGen:
                                "frontier replaces the input; its buffer is reused)" % (line, fr[1], fr[1], out_name))
         self.notes.append("frontier %s: `delete %s; %s = %s;` -> double-buffer swap, no allocation in the loop"
                           % (fr[1], fr[1], fr[1], out_name))
+        if self.blocked(label):
+            raise CompileError("line %d: EdgeBlocking applies when every edge is processed (edges.apply), "
+                               "not to a frontier operator" % line)
         sname = self.sched(label)
         push = self.edge_functor_for(udf, "push", filt, tracked)
         pull = self.edge_functor_for(udf, "pull", filt, tracked)
@@ -822,6 +832,16 @@ class MainGen:
         elif name == "apply" and target == ("id", self.prog.vertices):
             cname = self.vertex_functor_for(args[0][1])
             self.emit("gen::vertices_apply(c, g.n, %s%s);" % (cname, self.init_list(False)), depth)
+        elif name == "apply" and target == ("id", self.prog.edges["name"]) and self.blocked(label):
+            s1 = self.scheds[label]["s1"]
+            if s1["direction"] != "GG_PUSH" or self.scheds[label]["hybrid"]:
+                raise CompileError("line %d: EdgeBlocking runs EDGE_ONLY in the PUSH direction" % line)
+            self.sched(label)
+            push = self.edge_functor_for(args[0][1], "push", None, None)
+            self.emit("gen::all_edges_blocked(c, G, %d, %s%s);" % (s1["blocking_size"], push, self.init_list(True)),
+                      depth)
+            self.notes.append("edges.apply at line %d: EdgeBlocking, destination segments of %d vertices"
+                              % (line, s1["blocking_size"]))
         elif name == "apply" and target == ("id", self.prog.edges["name"]):
             sname = self.sched(label)
             push = self.edge_functor_for(args[0][1], "push", None, None)

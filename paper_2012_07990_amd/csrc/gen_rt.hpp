@@ -206,6 +206,36 @@ void all_edges_step(Ctx &c, const DevGraph &g, Workspace &ws, const int32_t *ids
 }
 
 
+// edges.apply(f) under EdgeBlocking (configLoadBalance(EDGE_ONLY, BLOCKED, N)):
+// every edge of the EdgeBlocked COO (destination segments of N vertices,
+// built once per graph and width), one launch per segment. f reads the
+// weights in the blocked order.
+template <class F>
+__global__ __launch_bounds__(kBlock) void k_gen_edges_blocked(const int32_t *src, const int32_t *dst, long long lo,
+                                                              long long hi, F f) {
+    for (long long e = lo + (long long)blockIdx.x * kBlock + threadIdx.x; e < hi; e += (long long)gridDim.x * kBlock)
+        (void)f.edge(src[e], dst[e], (int)e);
+}
+
+template <class F>
+void all_edges_blocked(Ctx &c, Graph &G, int32_t N, F f) {
+    edgeblock_prepare(c, G, N);
+    const EdgeBlocked *eb;
+    {
+        std::lock_guard<std::mutex> lk(G.mu);
+        eb = G.eb.at(N).get();
+    }
+    f.w = eb->w.p;
+    for (size_t sg = 0; sg + 1 < eb->seg_start.size(); sg++) {
+        const long long lo = eb->seg_start[sg], hi = eb->seg_start[sg + 1];
+        if (hi <= lo) continue;
+        hipLaunchKernelGGL(k_gen_edges_blocked<F>, dim3(blocks_for(hi - lo, kBlock, 16384)), dim3(kBlock), 0, c.s,
+                           eb->src.p, eb->dst.p, lo, hi, f);
+        GG_CHECK_LAUNCH();
+        c.launches++;
+    }
+}
+
 // ---- kernel fusion: the whole frontier loop in one persistent launch ----------
 
 struct GenFusedArgs {

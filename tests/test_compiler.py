@@ -169,10 +169,15 @@ def test_fused_loop_hoisting():
     assert "while (fs.count > 0)" in code and "k_fused_" not in code
 
 
-def test_edge_blocking_refused():
+def test_edge_blocking():
+    # every edge processed (edges.apply): the EdgeBlocked COO, one launch per segment
+    code, notes = gen("pagerank_push_blocked")
+    assert "gen::all_edges_blocked(c, G, 1000, E_updateEdge_push{" in code
+    assert any("destination segments of 1000 vertices" in n for n in notes)
+    # a frontier operator processes a frontier's edges only: refused
     src = variant_source("cc_push_edge_only").replace("configLoadBalance(EDGE_ONLY)",
                                                       "configLoadBalance(EDGE_ONLY, BLOCKED, 65536)")
-    with pytest.raises(CompileError, match="EdgeBlocking"):
+    with pytest.raises(CompileError, match="every edge is processed"):
         compile_source(src, ["IDs"])
 
 

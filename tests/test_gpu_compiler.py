@@ -119,7 +119,7 @@ def test_generated_cc(variant, name):
     assert np.array_equal(ids, oracle.cc(g.n, g.row_ptr, g.col))
 
 
-@pytest.mark.parametrize("variant", ["pagerank_pull", "pagerank_push_strict"])
+@pytest.mark.parametrize("variant", ["pagerank_pull", "pagerank_push_strict", "pagerank_push_blocked"])
 @pytest.mark.parametrize("name", SYM + ["drmat12"])
 def test_generated_pagerank(variant, name):
     g = host(name)
