@@ -147,8 +147,8 @@ def sweep_schedules(gg):
         out["sssp"]["strict-d%d" % d] = gg.make_schedule(lb="strict", delta=d)
         out["sssp"]["fused-strict-d%d" % d] = gg.make_schedule(lb="strict", delta=d, fusion=True)
     out["cc"]["fused-strict"] = gg.make_schedule(lb="strict", fusion=True)
-    for th in [0.01, 0.05, 0.1, 0.2]:
-        for N in [1 << 20, 1 << 21]:
+    for th in [0.01, 0.05, 0.1, 0.2, 0.3]:
+        for N in [1 << 18, 1 << 19, 1 << 20, 1 << 21]:
             for cr, tag in [(gg.CREATE_FUSED, "q"), (gg.CREATE_UNFUSED_BOOLMAP, "bool")]:
                 out["sssp"]["hybrid-strict-eb%d-%s-%g" % (N, tag, th)] = gg.make_schedule(
                     lb="strict", delta=4096, threshold=th,
