@@ -279,8 +279,6 @@ void bfs_run_ws(Graph &G, Workspace &wsr, int32_t src, const gg_schedule &s, int
         return;
     }
     FrontierState fs(c, *ws, g.n, g.n);
-    ws->tags.ensure((size_t)g.n);
-    fill_i32(c, ws->tags.p, g.n, 0);
     hipLaunchKernelGGL(k_bfs_init, dim3(blocks_for(g.n, kBlock, 8192)), dim3(kBlock), 0, c.s, depth, g.n, src,
                        fs.queue());
     GG_CHECK_LAUNCH();
@@ -292,7 +290,10 @@ void bfs_run_ws(Graph &G, Workspace &wsr, int32_t src, const gg_schedule &s, int
         if (st) st->vertices_processed += fs.count;
         if (sc.direction == GG_PUSH) {
             const int32_t *q = fs.as_queue();
-            const int dd = dedup_mode(sc);
+            // the CAS hands each vertex to one edge per round, so the output
+            // queue holds no duplicates for deduplication to remove (as in the
+            // fused kernel and BC's push)
+            const int dd = kDedupNone;
             OutFrontier o = fs.prep_out(sc.frontier_creation, dd, level + 1);
             PushPlan p{sc.load_balance, sc.frontier_creation, dd};
             push_apply(c, g, *ws, p, q, fs.count, BfsPush{depth, level + 1}, o, member_map(*ws, g.n, p.lb));

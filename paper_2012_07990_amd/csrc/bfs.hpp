@@ -16,9 +16,19 @@ struct BfsPush {
     // load balancers batch the loads of several edges before applying them
     using Pre = int;
     __device__ __forceinline__ Pre load(int, int v, int) const { return depth[v]; }
-    __device__ __forceinline__ int apply(int, int v, int, Pre dv) const {
-        if (dv >= 0) return -1;  // filter (a stale read only costs a failed CAS)
-        return atomic_cas_i32(&depth[v], -1, next) == -1 ? v : -1;
+    // two-phase form: the CAS's old value, else the loaded depth (a value the
+    // compiler cannot fold, so the result test stays out of the CAS's branch)
+    using Tok = int;
+    __device__ __forceinline__ Tok issue(int, int v, int, Pre dv, bool ok) const {
+        int r = dv;
+        if (ok && dv < 0) r = atomic_cas_i32(&depth[v], -1, next);  // filter: a stale read only costs a failed CAS
+        return r;
+    }
+    __device__ __forceinline__ int finish(int, int v, int, Pre, bool ok, Tok r) const {
+        return ok && r == -1 ? v : -1;
+    }
+    __device__ __forceinline__ int apply(int u, int v, int e, Pre dv) const {
+        return finish(u, v, e, dv, true, issue(u, v, e, dv, true));
     }
     __device__ __forceinline__ int edge(int u, int v, int e) const { return apply(u, v, e, load(u, v, e)); }
     __device__ __forceinline__ void begin() const {}

@@ -53,6 +53,48 @@ __device__ __forceinline__ bool dedup_first(const OutFrontier &o, int v) {
     }
 }
 
+// dedup_first over a lane's batch of B candidates (want[b] in: x[b] is a
+// candidate; out: x[b] is its first enqueue this round). All tag reads are
+// issued, then all atomics, then the results are read: each atomic's result
+// starts out as the value read (a value the compiler cannot fold), so the
+// result test is not moved into the atomic's branch, where it would make the
+// lane wait for every atomic in turn.
+template <int DEDUP, int B>
+__device__ __forceinline__ void dedup_batch(const OutFrontier &o, const int *x, bool *want) {
+    if constexpr (DEDUP == kDedupMonotonic) {
+        int r[B];
+#pragma unroll
+        for (int b = 0; b < B; b++) r[b] = want[b] ? o.tags[x[b]] : o.iter;
+#pragma unroll
+        for (int b = 0; b < B; b++)
+            if (want[b] && r[b] < o.iter) r[b] = atomic_max_i32(&o.tags[x[b]], o.iter);
+#pragma unroll
+        for (int b = 0; b < B; b++) want[b] = want[b] && r[b] < o.iter;
+    } else if constexpr (DEDUP == kDedupBitmap) {
+        unsigned long long r[B];
+#pragma unroll
+        for (int b = 0; b < B; b++) r[b] = want[b] ? o.dedup_bits[x[b] >> 6] : ~0ull;
+#pragma unroll
+        for (int b = 0; b < B; b++) {
+            const unsigned long long bit = 1ull << (x[b] & 63);
+            if (want[b] && !(r[b] & bit)) r[b] = atomic_or_u64(&o.dedup_bits[x[b] >> 6], bit);
+        }
+#pragma unroll
+        for (int b = 0; b < B; b++) want[b] = want[b] && !((r[b] >> (x[b] & 63)) & 1ull);
+    } else if constexpr (DEDUP == kDedupBoolmap) {
+        unsigned r[B];
+#pragma unroll
+        for (int b = 0; b < B; b++) r[b] = want[b] ? o.dedup_bytes[x[b] >> 2] : ~0u;
+#pragma unroll
+        for (int b = 0; b < B; b++) {
+            const unsigned sh = (unsigned)(x[b] & 3) * 8u;
+            if (want[b] && !((r[b] >> sh) & 1u)) r[b] = atomic_or_u32(&o.dedup_bytes[x[b] >> 2], 1u << sh);
+        }
+#pragma unroll
+        for (int b = 0; b < B; b++) want[b] = want[b] && !((r[b] >> ((unsigned)(x[b] & 3) * 8u)) & 1u);
+    }
+}
+
 // Wave-aggregated append: one atomic per wavefront, lanes write at
 // base + (number of wanting lanes below them). Every active lane of the
 // wave must call this together.
@@ -115,6 +157,58 @@ __device__ __forceinline__ void stage_flush(const Staged &st, int32_t cap, int32
     __syncthreads();
 }
 
+// B appends per lane at once (lane l wants v[b] when want[b]). Every lane of
+// the wavefront must call this together: the lanes' counts are placed with one
+// scan and one LDS atomic per wavefront, and the slots past the stage with one
+// global atomic. st.sq must have kStage + 1 slots (StageLDS's do).
+template <int B>
+__device__ __forceinline__ void stage_append_batch(const Staged &st, int32_t cap, int32_t *overflow, const int *v,
+                                                   const bool *want) {
+    int k = 0;
+#pragma unroll
+    for (int b = 0; b < B; b++) k += want[b];
+    const int incl = wave_incl_scan(k);
+    const int total = wave_bcast(incl, kWave - 1);
+    if (total == 0) return;
+    int base = 0;
+    if (lane_id() == kWave - 1)
+        base = __hip_atomic_fetch_add(st.sc, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    base = wave_bcast(base, kWave - 1);
+    // slots [lo, base + total) lie past the stage: one global reservation for
+    // all of them (a hub's walk can fill the stage long before a flush)
+    const int lo = base > kStage ? base : kStage;
+    const int n_over = base + total - lo;
+    int gbase = 0;
+    if (n_over > 0) {
+        if (lane_id() == kWave - 1) gbase = atomic_add_i32(st.count, n_over);
+        gbase = wave_bcast(gbase, kWave - 1);
+    }
+    int pos = base + incl - k;
+    if (n_over <= 0) {
+        // all of the wavefront's slots are in the stage: unwanted items write
+        // the sink slot sq[kStage], so no item needs a branch
+#pragma unroll
+        for (int b = 0; b < B; b++) {
+            st.sq[want[b] ? pos : kStage] = v[b];
+            pos += want[b];
+        }
+        return;
+    }
+#pragma unroll
+    for (int b = 0; b < B; b++) {
+        if (want[b]) {
+            if (pos < kStage) {
+                st.sq[pos] = v[b];
+            } else {
+                const int q = gbase + (pos - lo);
+                if (q < cap) st.q[q] = v[b];
+                else *overflow = 1;
+            }
+        }
+        pos += want[b];
+    }
+}
+
 // Output-frontier sink used inside edge loops (FUSED creation calls the
 // wave-aggregated append; the unfused forms mark a dense map).
 template <int CREATE, int DEDUP>
@@ -133,7 +227,7 @@ __device__ __forceinline__ void emit(const OutFrontier &o, bool want, int v) {
 // forms need no queue). `s` is the workgroup's LDS stage; the caller flushes
 // it at workgroup-uniform points.
 struct StageLDS {
-    int32_t q[kStage];
+    int32_t q[kStage + 1];  // the last slot takes the batch appends' discarded writes
     int c, base;
 };
 
@@ -144,6 +238,22 @@ __device__ __forceinline__ void emit_staged(const OutFrontier &o, StageLDS &s, b
         stage_append(Staged{s.q, &s.c, o.q, o.count}, o.cap, o.overflow, want, v);
     } else {
         emit<CREATE, DEDUP>(o, want, v);
+    }
+}
+
+// emit_staged for a lane's batch of B results (x[b] >= 0: append x[b]); every
+// lane of the wavefront calls it together
+template <int CREATE, int DEDUP, int B>
+__device__ __forceinline__ void emit_staged_batch(const OutFrontier &o, StageLDS &s, const int *x) {
+    if constexpr (CREATE == kCreateFused) {
+        bool want[B];
+#pragma unroll
+        for (int b = 0; b < B; b++) want[b] = x[b] >= 0;
+        dedup_batch<DEDUP, B>(o, x, want);
+        stage_append_batch<B>(Staged{s.q, &s.c, o.q, o.count}, o.cap, o.overflow, x, want);
+    } else {
+#pragma unroll
+        for (int b = 0; b < B; b++) emit<CREATE, DEDUP>(o, x[b] >= 0, x[b]);
     }
 }
 

@@ -27,10 +27,53 @@
 //   bool done(x)            -- stop scanning x's edges early (pull)
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "frontier.hpp"
 
 namespace gg {
+
+// Functors whose update is one atomic may split apply() in two: issue(..., ok)
+// makes the atomic (when ok and the filter passes) and returns its raw result
+// as a Tok, finish(..., ok, tok) turns that into apply()'s return value. A
+// batch then issues all its atomics before reading any result: with apply()
+// the result is compared inside the branch that guards the atomic, so the
+// compiler waits for each atomic before issuing the next.
+template <class F, class = void>
+struct TwoPhase : std::false_type {};
+template <class F>
+struct TwoPhase<F, std::void_t<typename F::Tok>> : std::true_type {};
+
+// the updates of a batch of B edges (uu[b], vv[b], ee[b]) with their loaded
+// values pp[b]; ok[b] false skips an edge. xx[b] gets apply()'s result or -1.
+template <int B, class F>
+__device__ __forceinline__ void apply_batch(F &f, const int *uu, const int *vv, const int *ee,
+                                            const typename F::Pre *pp, const bool *ok, int *xx, long long &ne) {
+    if constexpr (TwoPhase<F>::value) {
+        typename F::Tok tk[B];
+        bool go[B];
+#pragma unroll
+        for (int b = 0; b < B; b++) {
+            go[b] = ok[b] && !f.done(uu[b]);
+            tk[b] = f.issue(uu[b], vv[b], ee[b], pp[b], go[b]);
+        }
+#pragma unroll
+        for (int b = 0; b < B; b++) {
+            xx[b] = f.finish(uu[b], vv[b], ee[b], pp[b], go[b], tk[b]);
+            ne += go[b];
+        }
+    } else {
+#pragma unroll
+        for (int b = 0; b < B; b++) {
+            xx[b] = -1;
+            if (ok[b] && !f.done(uu[b])) {
+                xx[b] = f.apply(uu[b], vv[b], ee[b], pp[b]);
+                ne++;
+            }
+        }
+    }
+}
 
 // Edges a lane loads before applying them (load-balancer loops that issue
 // each edge's column and functor reads for several edges at once, so their
@@ -43,12 +86,16 @@ struct Tid {  // position of this lane in the (possibly persistent) grid
 };
 
 // ---------------------------------------------------------------------------- VP
-// One lane per frontier vertex walks its edges, kVpBatch at a time: their
-// column reads, then their functor reads, then their updates are each issued
-// back to back, so a hub's serial walk pays three memory round trips per
-// kVpBatch edges. Appends are staged per workgroup unless STAGE is false
-// (see lb_cm).
+// One lane per frontier vertex walks its edges a batch at a time: the
+// batch's column reads, then its functor reads, then its updates are each
+// issued back to back, so a hub's serial walk pays three memory round trips
+// per batch. Appends are staged per workgroup unless STAGE is false (see
+// lb_cm); the staged form takes larger batches when the functor
+// loads one word per edge (a hub's walk is the launch's critical path); the
+// unstaged one runs inside persistent kernels, where registers bound the
+// resident grid.
 constexpr int kVpBatch = 16;
+constexpr int kVpBatchStaged = 32;
 template <int CREATE, int DEDUP, bool STAGE = true, class Src, class F>
 __device__ void lb_vp(const DevGraph &g, const Src &src, F &f, const OutFrontier &out, Tid t,
                       long long &ne) {
@@ -62,32 +109,43 @@ __device__ void lb_vp(const DevGraph &g, const Src &src, F &f, const OutFrontier
     for (int base = t.block * kBlock; base < src.size; base += stride) {
         const int i = base + (int)threadIdx.x;
         const int u = i < src.size ? src.get(i) : 0;
+        int e0 = 0, end = 0;
         if (i < src.size && f.active(u)) {
-            const int end = g.row_ptr[u + 1];
-            for (int e0 = g.row_ptr[u]; e0 < end && !f.done(u); e0 += kVpBatch) {
-                int vv[kVpBatch];
-                typename F::Pre pp[kVpBatch];
+            e0 = g.row_ptr[u];
+            end = g.row_ptr[u + 1];
+        }
+        // the wavefront takes batches until its longest row is done, every
+        // lane in every batch (lanes out of edges apply nothing), so a batch's
+        // appends are placed with one scan over the wavefront
+        constexpr int B = STAGE && sizeof(typename F::Pre) <= 4 ? kVpBatchStaged : kVpBatch;
+        for (;;) {
+            const bool has = e0 < end && !f.done(u);
+            if (__ballot(has) == 0) break;
+            int vv[B], xx[B], uu[B], ee[B];
+            typename F::Pre pp[B];
+            bool ok[B];
 #pragma unroll
-                for (int b = 0; b < kVpBatch; b++) vv[b] = g.col[e0 + b < end ? e0 + b : end - 1];
-#pragma unroll
-                for (int b = 0; b < kVpBatch; b++) pp[b] = f.load(u, vv[b], e0 + b < end ? e0 + b : end - 1);
-                // every update of the batch (its atomics) is issued before any
-                // result is consumed by an append
-                int xx[kVpBatch];
-#pragma unroll
-                for (int b = 0; b < kVpBatch; b++) {
-                    xx[b] = -1;
-                    if (e0 + b < end && !f.done(u)) {
-                        xx[b] = f.apply(u, vv[b], e0 + b, pp[b]);
-                        ne++;
-                    }
-                }
-#pragma unroll
-                for (int b = 0; b < kVpBatch; b++) {
-                    if constexpr (STAGE) emit_staged<CREATE, DEDUP>(out, s_st, xx[b] >= 0, xx[b]);
-                    else emit<CREATE, DEDUP>(out, xx[b] >= 0, xx[b]);
-                }
+            for (int b = 0; b < B; b++) {
+                vv[b] = 0;
+                pp[b] = typename F::Pre{};
+                uu[b] = u;
+                ee[b] = e0 + b;
+                ok[b] = has && e0 + b < end;
             }
+            if (has) {
+#pragma unroll
+                for (int b = 0; b < B; b++) vv[b] = g.col[e0 + b < end ? e0 + b : end - 1];
+#pragma unroll
+                for (int b = 0; b < B; b++) pp[b] = f.load(u, vv[b], e0 + b < end ? e0 + b : end - 1);
+            }
+            apply_batch<B>(f, uu, vv, ee, pp, ok, xx, ne);
+            if constexpr (STAGE) {
+                emit_staged_batch<CREATE, DEDUP, B>(out, s_st, xx);
+            } else {
+#pragma unroll
+                for (int b = 0; b < B; b++) emit<CREATE, DEDUP>(out, xx[b] >= 0, xx[b]);
+            }
+            if (has) e0 += B;
         }
         if constexpr (STAGE) {
             emit_flush_half<CREATE>(out, s_st);
@@ -256,15 +314,15 @@ __device__ void lb_etwc(const DevGraph &g, const Src &src, F &f, const OutFronti
                 for (int b = 0; b < kEdgeBatch; b++) vv[b] = g.col[e0 + b < end ? e0 + b : end - 1];
 #pragma unroll
                 for (int b = 0; b < kEdgeBatch; b++) pp[b] = f.load(u, vv[b], e0 + b < end ? e0 + b : end - 1);
-                int xx[kEdgeBatch];
+                int xx[kEdgeBatch], uu[kEdgeBatch], ee[kEdgeBatch];
+                bool ok[kEdgeBatch];
 #pragma unroll
                 for (int b = 0; b < kEdgeBatch; b++) {
-                    xx[b] = -1;
-                    if (e0 + b < end && !f.done(u)) {
-                        xx[b] = f.apply(u, vv[b], e0 + b, pp[b]);
-                        ne++;
-                    }
+                    uu[b] = u;
+                    ee[b] = e0 + b;
+                    ok[b] = e0 + b < end;
                 }
+                apply_batch<kEdgeBatch>(f, uu, vv, ee, pp, ok, xx, ne);
 #pragma unroll
                 for (int b = 0; b < kEdgeBatch; b++) {
                     if constexpr (STAGE) emit_staged<CREATE, DEDUP>(out, s_st, xx[b] >= 0, xx[b]);
@@ -468,14 +526,10 @@ __device__ void lb_strict(const DevGraph &g, const Src &src, const long long *sc
 #pragma unroll
                 for (int k = 0; k < kEdgeBatch; k++) pp[k] = f.load(uu[k], vv[k], ee[k]);
                 int xx[kEdgeBatch];
+                bool ok[kEdgeBatch];
 #pragma unroll
-                for (int k = 0; k < kEdgeBatch; k++) {
-                    xx[k] = -1;
-                    if (rb + (long long)k * kBlock < hi && !f.done(uu[k])) {
-                        xx[k] = f.apply(uu[k], vv[k], ee[k], pp[k]);
-                        ne++;
-                    }
-                }
+                for (int k = 0; k < kEdgeBatch; k++) ok[k] = rb + (long long)k * kBlock < hi;
+                apply_batch<kEdgeBatch>(f, uu, vv, ee, pp, ok, xx, ne);
 #pragma unroll
                 for (int k = 0; k < kEdgeBatch; k++) emit_staged<CREATE, DEDUP>(out, s_st, xx[k] >= 0, xx[k]);
             }

@@ -46,19 +46,30 @@ struct SsspRelaxT {
         return Pre{(long long)dist[u] + (long long)w[e], dist[v]};
     }
     __device__ __forceinline__ int edge(int u, int v, int e) const { return apply(u, v, e, load(u, v, e)); }
-    __device__ __forceinline__ int apply(int, int v, int, const Pre &p) const {
+    // two-phase form: the atomic minimum's old distance, else the loaded one
+    // (no smaller than the candidate then, and a value the compiler cannot
+    // fold, so the result test stays out of the atomic's branch)
+    using Tok = int;
+    __device__ __forceinline__ Tok issue(int, int v, int, const Pre &p, bool ok) const {
+        int old = p.dv;
+        // a stale (larger) read only costs an atomic
+        if (ok && p.nd <= (long long)INT_MAX - 1 && p.nd < p.dv) old = atomic_min_i32(&dist[v], (int)p.nd);
+        return old;
+    }
+    __device__ __forceinline__ int apply(int u, int v, int e, const Pre &p) const {
+        return finish(u, v, e, p, true, issue(u, v, e, p, true));
+    }
+    __device__ __forceinline__ int finish(int, int v, int, const Pre &p, bool ok, Tok old) const {
         const long long nd = p.nd;
         bool to_near = false, to_far = false;
-        if (nd > (long long)INT_MAX - 1) {
+        if (!ok) {
+        } else if (nd > (long long)INT_MAX - 1) {
             // not representable: v is unreached so far and may end up with a
             // distance beyond INT32_MAX-1 (confirmed after the loop)
             if (p.dv == INT_MAX) flags[0] = 1;
-        } else if (nd < p.dv) {  // a stale (larger) read only costs an atomic
-            const int old = atomic_min_i32(&dist[v], (int)nd);
-            if (nd < old) {
-                if (nd < bucket_end) to_near = true;
-                else to_far = far_tag[v] < far_id && atomic_max_i32(&far_tag[v], far_id) < far_id;
-            }
+        } else if (nd < old) {
+            if (nd < bucket_end) to_near = true;
+            else to_far = far_tag[v] < far_id && atomic_max_i32(&far_tag[v], far_id) < far_id;
         }
         if constexpr (STAGE) stage_append(sssp_far_stage(farq, farc), far_cap, flags + 1, to_far, v);
         else wave_append(farq, farc, far_cap, flags + 1, to_far, v);
@@ -332,15 +343,12 @@ __global__ __launch_bounds__(kBlock) void k_sssp_push_blocked(const int32_t *src
 #pragma unroll
         for (int b = 0; b < kEdgeBatch; b++)
             pre[b] = take[b] ? f.load(uu[b], vv[b], (int)(e0 + b * stride)) : SsspRelaxT<false>::Pre{0, 0};
+        int ee[kEdgeBatch], xx[kEdgeBatch];
 #pragma unroll
-        for (int b = 0; b < kEdgeBatch; b++) {
-            int x = -1;
-            if (take[b]) {
-                x = f.apply(uu[b], vv[b], (int)(e0 + b * stride), pre[b]);
-                ne++;
-            }
-            emit_staged<CREATE, DEDUP>(out, s_st, x >= 0, x);
-        }
+        for (int b = 0; b < kEdgeBatch; b++) ee[b] = (int)(e0 + b * stride);
+        apply_batch<kEdgeBatch>(f, uu, vv, ee, pre, take, xx, ne);
+#pragma unroll
+        for (int b = 0; b < kEdgeBatch; b++) emit_staged<CREATE, DEDUP>(out, s_st, xx[b] >= 0, xx[b]);
         emit_flush_half<CREATE>(out, s_st);
     }
     emit_flush<CREATE>(out, s_st);
