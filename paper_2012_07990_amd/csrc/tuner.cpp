@@ -3,7 +3,8 @@
 // hybrid threshold x frontier representation and creation x deduplication x
 // kernel fusion x delta x EdgeBlocking width -- are timed on the graph and
 // narrowed by successive halving (every round keeps the faster half and
-// doubles the number of timed runs per survivor) within a wall-clock budget.
+// doubles the number of probe sources each survivor is timed on) within a
+// wall-clock budget.
 // The winner is cached on the graph per algorithm.
 #include <hip/hip_runtime.h>
 
@@ -232,28 +233,39 @@ gg_schedule autotune(Graph &G, int algo, double budget_s, const int32_t *probes,
             }
     }
     t0 = std::chrono::steady_clock::now();  // the search budget starts here
+    // A candidate's time in a round is the sum over that round's sources (the
+    // same sources for every candidate), so a schedule that is slow on some
+    // sources loses even when it is fast on others; the first round runs each
+    // candidate once untimed first (a workspace grown on first use).
     int runs = 1, probe_i = 0;
+    bool first = true;
     while (cands.size() > 1) {
+        size_t timed = 0;
         for (auto &c : cands) {
-            double best = 1e30;
-            for (int r = 0; r < runs; r++) {
-                const int src = srcs[(probe_i + r) % srcs.size()];
-                try {
-                    best = std::min(best, time_one(G, algo, c.s, src, o1.p, o2.p, st));
-                } catch (const Error &e) {
-                    if (e.code == GG_ERR_DEVICE) throw;
-                    best = 1e30;  // e.g. a queue overflow without dedup: not a usable schedule
-                    break;
+            double sum = 0;
+            try {
+                if (first) time_one(G, algo, c.s, srcs[0], o1.p, o2.p, st);
+                for (int r = 0; r < runs; r++) {
+                    const int src = srcs[(probe_i + r) % srcs.size()];
+                    sum += time_one(G, algo, c.s, src, o1.p, o2.p, st);
                 }
+            } catch (const Error &e) {
+                if (e.code == GG_ERR_DEVICE) throw;
+                sum = 1e30;  // e.g. a queue overflow without dedup: not a usable schedule
             }
-            c.t = best;
-            if (elapsed() > budget_s && &c != &cands.front()) break;
+            c.t = sum / runs;
+            timed++;
+            if (elapsed() > budget_s) break;
         }
+        // a round cut short by the budget: only the candidates it timed (the
+        // front of the previous ranking) compete, on the same sources
+        if (timed < cands.size()) cands.resize(timed);
         std::stable_sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.t < b.t; });
         if (elapsed() > budget_s) break;
         cands.resize((cands.size() + 1) / 2);
+        probe_i += runs;
         runs *= 2;
-        probe_i += 1;
+        first = false;
     }
     const Cand &w = cands.front();
     if (best_ms) *best_ms = w.t * 1e3;
