@@ -294,7 +294,7 @@ void bfs_run_ws(Graph &G, Workspace &wsr, int32_t src, const gg_schedule &s, int
             // queue holds no duplicates for deduplication to remove (as in the
             // fused kernel and BC's push)
             const int dd = kDedupNone;
-            OutFrontier o = fs.prep_out(sc.frontier_creation, dd, level + 1);
+            OutFrontier o = fs.prep_out(sc.frontier_creation, dd, level + 1, sc.load_balance);
             PushPlan p{sc.load_balance, sc.frontier_creation, dd};
             push_apply(c, g, *ws, p, q, fs.count, BfsPush{depth, level + 1}, o, member_map(*ws, g.n, p.lb));
             fs.commit(sc.frontier_creation);

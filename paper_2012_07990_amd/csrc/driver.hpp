@@ -70,12 +70,15 @@ struct FrontierState {
         return ws.bitmap[ti].p;
     }
 
-    // Output frontier for a push with the given creation/dedup mode.
-    OutFrontier prep_out(int create, int dedup, int iter) {
+    // Output frontier for a push with the given creation/dedup mode. With
+    // FUSED creation under STRICT (lb) the output count is zeroed by the degree
+    // scan that precedes the push instead of a launch of its own.
+    OutFrontier prep_out(int create, int dedup, int iter, int lb = -1) {
         OutFrontier o{};
         o.overflow = cnt(2);
         if (create == kCreateFused) {
-            fill_i32(c, cnt(0), 1, 0);
+            if (lb == GG_LB_STRICT) o.clear = cnt(0);
+            else fill_i32(c, cnt(0), 1, 0);
             o.q = ws.q[qi ^ 1].p;
             o.count = cnt(0);
             o.cap = (int32_t)qcap;

@@ -30,6 +30,8 @@ struct OutFrontier {
     int32_t iter;            // MONOTONIC_COUNTERS: id of this iteration (>= 1)
     unsigned long long *dedup_bits;  // BITMAP dedup (cleared every round)
     unsigned *dedup_bytes;   // BOOLMAP dedup, bytes packed 4 per word (cleared every round)
+    int32_t *clear;          // FUSED: `count` when its creator left zeroing it to the traversal's
+                             // first kernel (STRICT's degree scan), else null
 };
 
 // Each test reads the tag first and skips the atomic when v is already

@@ -267,9 +267,25 @@ __global__ __launch_bounds__(1024) void k_scan_partials(long long *partials, int
     }
 }
 
+// partials: per-tile degree sums from k_scan_reduce, which each workgroup adds
+// up for the tiles before it (scanned false: up to kInlineTiles tiles), or
+// their exclusive scan (scanned true), or null for a single tile. zero: a
+// counter to clear on the way (the next push's output count).
+constexpr int kInlineTiles = 4096;
 __global__ __launch_bounds__(kBlock) void k_scan_apply(DevGraph g, const int32_t *q, int count,
-                                                       const long long *partials, long long *scan) {
+                                                       const long long *partials, bool scanned, long long *scan,
+                                                       int32_t *zero) {
     __shared__ long long s_w[kBlock / kWave];
+    __shared__ long long s_tmp[kBlock / kWave];
+    if (zero != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *zero = 0;
+    long long off = 0;
+    if (partials != nullptr && scanned) {
+        off = partials[blockIdx.x];
+    } else if (partials != nullptr) {
+        long long t = 0;
+        for (int j = threadIdx.x; j < (int)blockIdx.x; j += kBlock) t += partials[j];
+        off = block_sum_ll(t, s_tmp);
+    }
     const long long base = (long long)blockIdx.x * kScanTile;
     // each lane owns kScanItems consecutive entries
     const long long first = base + (long long)threadIdx.x * kScanItems;
@@ -289,7 +305,6 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(DevGraph g, const int32_t
     const long long incl = wave_incl_scan64(s);
     if (lane_id() == kWave - 1) s_w[threadIdx.x / kWave] = incl;
     __syncthreads();
-    long long off = partials[blockIdx.x];
     for (int w = 0; w < (int)(threadIdx.x / kWave); w++) off += s_w[w];
     long long run = off + incl - s;
 #pragma unroll
@@ -305,16 +320,24 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(DevGraph g, const int32_t
 size_t degree_scan_partials(int count) { return (size_t)(count + kScanTile - 1) / kScanTile + 1; }
 
 void degree_scan(Ctx &c, const DevGraph &g, const int32_t *q, int count, long long *scan,
-                 long long *partials) {
+                 long long *partials, int32_t *zero) {
     // tiles cover [0, count] inclusive so the total lands in scan[count]
     const int tiles = (count + 1 + kScanTile - 1) / kScanTile;
-    hipLaunchKernelGGL(k_scan_reduce, dim3(tiles), dim3(kBlock), 0, c.s, g, q, count, partials);
+    const bool scanned = tiles > kInlineTiles;
+    if (tiles > 1) {
+        hipLaunchKernelGGL(k_scan_reduce, dim3(tiles), dim3(kBlock), 0, c.s, g, q, count, partials);
+        GG_CHECK_LAUNCH();
+        c.launches++;
+    }
+    if (scanned) {
+        hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, c.s, partials, tiles);
+        GG_CHECK_LAUNCH();
+        c.launches++;
+    }
+    hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(kBlock), 0, c.s, g, q, count,
+                       (const long long *)(tiles > 1 ? partials : nullptr), scanned, scan, zero);
     GG_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, c.s, partials, tiles);
-    GG_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(kBlock), 0, c.s, g, q, count, partials, scan);
-    GG_CHECK_LAUNCH();
-    c.launches += 3;
+    c.launches++;
 }
 
 int32_t read_i32(Ctx &c, const int32_t *dev, int32_t *pinned) {

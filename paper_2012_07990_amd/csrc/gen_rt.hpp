@@ -138,7 +138,7 @@ void frontier_step(Ctx &c, const DevGraph &g, Workspace &ws, FrontierState &fs, 
     if (sc.direction == GG_PUSH) {
         const int32_t *q = fs.as_queue();
         const int dd = dedup_mode(sc);
-        OutFrontier o = fs.prep_out(sc.frontier_creation, dd, iter);
+        OutFrontier o = fs.prep_out(sc.frontier_creation, dd, iter, sc.load_balance);
         const PushPlan p{sc.load_balance, sc.frontier_creation, dd};
         push_apply(c, g, ws, p, q, fs.count, f, o, member_map(ws, g.n, p.lb));
         fs.commit(sc.frontier_creation);

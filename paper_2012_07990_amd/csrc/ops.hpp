@@ -271,9 +271,10 @@ void bitmap_to_queue(Ctx &c, const unsigned long long *map, int n, int32_t *q, i
 // population counts into a device int (zeroed by the caller)
 void count_boolmap(Ctx &c, const uint8_t *map, int n, int32_t *count);
 void count_bitmap(Ctx &c, const unsigned long long *map, int n, int32_t *count);
-// exclusive scan of the degrees of q[0..count) into scan[0..count] (int64)
+// exclusive scan of the degrees of q[0..count) into scan[0..count] (int64);
+// zeroes *zero too when it is not null (one or two launches)
 void degree_scan(Ctx &c, const DevGraph &g, const int32_t *q, int count, long long *scan,
-                 long long *partials);
+                 long long *partials, int32_t *zero = nullptr);
 size_t degree_scan_partials(int count);
 // in place: data[0..n) counts -> data[0..n] exclusive offsets (int32 totals)
 void exclusive_scan_i32(Ctx &c, int32_t *data, int n, long long *partials);

@@ -444,7 +444,7 @@ void sssp_run(Graph &G, int32_t src, const gg_schedule &sch, int32_t *dist, hipS
                 continue;
             }
             const int32_t *q = fs.as_queue();
-            OutFrontier o = fs.prep_out(sr.frontier_creation, ddr, iter++);
+            OutFrontier o = fs.prep_out(sr.frontier_creation, ddr, iter++, sr.load_balance);
             const PushPlan plan{sr.load_balance, sr.frontier_creation, ddr};
             const int lbm = sr.load_balance;
             if (lbm == GG_LB_STRICT || lbm == GG_LB_CM || lbm == GG_LB_ETWC || lbm == GG_LB_VERTEX_BASED) {

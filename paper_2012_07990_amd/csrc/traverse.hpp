@@ -78,7 +78,7 @@ static void launch_push_lb(Ctx &c, const DevGraph &g, Workspace &ws, const int32
         if constexpr (LB == GG_LB_STRICT) {
             ws.scan.ensure((size_t)qn + 1);
             ws.scan_part.ensure(degree_scan_partials(qn));
-            degree_scan(c, g, q, qn, ws.scan.p, ws.scan_part.p);
+            degree_scan(c, g, q, qn, ws.scan.p, ws.scan_part.p, out.clear);
             scan = ws.scan.p;
             blocks = (unsigned)c.num_cus * 8;
         }
@@ -116,7 +116,10 @@ static void launch_push_cd(Ctx &c, const DevGraph &g, Workspace &ws, int lb, con
 template <class F>
 void push_apply(Ctx &c, const DevGraph &g, Workspace &ws, const PushPlan &p, const int32_t *q, int qn, F f,
                 const OutFrontier &out, uint8_t *member) {
-    if (qn <= 0) return;
+    if (qn <= 0) {
+        if (out.clear) fill_i32(c, out.clear, 1, 0);
+        return;
+    }
     if (p.create == kCreateFused) {
         switch (p.dedup) {
         case kDedupNone: launch_push_cd<kCreateFused, kDedupNone>(c, g, ws, p.lb, q, qn, f, out, member); break;
