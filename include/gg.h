@@ -206,6 +206,9 @@ gg_status gg_schedule_validate(const gg_graph *g, int32_t algo, const gg_schedul
 /*
  * BFS from src: depth_dev[n] int32 receives the hop count, -1 when
  * unreachable (the depth is the unique part of the paper's parent-array BFS).
+ * A PUSH round claims each vertex with one CAS, so its output queue holds no
+ * duplicates: the schedule's deduplication setting changes nothing and is
+ * not applied.
  */
 gg_status gg_bfs(gg_graph *g, int32_t src, const gg_schedule *s, int32_t *depth_dev,
                  gg_stream_t stream, gg_stats *stats);
