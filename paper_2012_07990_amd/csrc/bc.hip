@@ -333,7 +333,9 @@ void bc_run(Graph &G, int32_t src, const gg_schedule &sch, uint64_t *sigma_out, 
         o.cap = n - off[L + 1];
         o.count = ctr + 0;
         o.overflow = ctr + 2;
-        fill_i32(c, ctr, 1, 0);
+        // a STRICT push clears the level's count in its degree scan
+        if (sc.direction == GG_PUSH && sc.load_balance == GG_LB_STRICT) o.clear = ctr;
+        else fill_i32(c, ctr, 1, 0);
         if (st) { st->iterations++; st->vertices_processed += cnt; }
         if (sc.direction == GG_PUSH) {
             push_apply(c, g, *ws, PushPlan{sc.load_balance, kCreateFused, kDedupNone}, order + off[L], cnt,
