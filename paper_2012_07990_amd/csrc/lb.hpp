@@ -25,6 +25,11 @@
 //   int  edge(x, y, e)      -- process edge e = (x, y); returns the vertex to
 //                              put in the output frontier, or -1
 //   bool done(x)            -- stop scanning x's edges early (pull)
+//   Pre load(x, y, e)       -- the edge's reads, no side effects (batched
+//   int apply(x, y, e, pre)    loops issue a batch's loads, then its applies)
+//   Tok issue(x, y, e, pre, ok), int finish(x, y, e, pre, ok, tok)
+//                           -- optional two-phase apply (see TwoPhase below)
+//   begin(), flush()        -- workgroup-uniform hooks around staged work
 #pragma once
 
 #include <type_traits>
